@@ -1,0 +1,161 @@
+"""Benchmark: time steps per second of the 512^3 FP64 Klein-Gordon stepper.
+
+Workload: 512^3 real grid on the periodic box [-4 pi, 4 pi)^3, Gaussian
+u0 = 0.1 exp(-(x^2 + y^2 + z^2)), u_t0 = 0, dt = 0.005, FP64, scheme of
+eq. (2).  A step is one pass of the whole hot path (x pass with the cubic
+term, forward y, z pass with the update and energy, inverse y, finalize).
+The initial field is resident in HBM before timing starts.
+
+Prints one JSON line.  Also reports the dominant kernel's roofline figures
+(its algorithmic bytes over its average launch time, measured with HIP
+events inside the timed steps) and the CPU oracle timed on a bounded sample
+(one 512^3 step) on this host.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--dt", type=float, default=0.005)
+    ap.add_argument("--amplitude", type=float, default=0.1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--energy-every", type=int, default=50)
+    return ap.parse_args()
+
+
+def traffic_from_profiles(n):
+    """Counter-derived HBM bytes per launch of the z pass, if a committed
+    measurement for this grid size exists (profiles/*counters*.json)."""
+    path = os.path.join(ROOT, "profiles", f"z_update_{n}_counters.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as f:
+            d = json.load(f)
+        if d.get("source_hash") != kernel_source_hash():
+            return None
+        return d.get("bytes_per_launch")
+    except Exception:
+        return None
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kg_fft.hpp", "kg_kernels.hpp"):
+        with open(os.path.join(ROOT, "paper_1501_04552_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def cpu_baseline(u0, dt):
+    """The oracle on this host: one step of the same workload (set-up excluded)."""
+    import oracle
+    r = oracle.run(u0, dt, 1)
+    secs = r["loop_seconds"]
+    return {"value": 1.0 / secs if secs > 0 else None, "unit": "steps/s",
+            "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"1 time step of the {u0.shape[0]}^3 FP64 workload (set-up excluded), "
+                      f"{secs:.2f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): this solver keeps the "
+              "whole grid on a single device and has no multi-GPU path.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import kg_inputs as ki
+    import paper_1501_04552_amd as kg
+
+    torch.cuda.set_device(0)
+    n, dt = args.n, args.dt
+    u0 = ki.gaussian(n, args.amplitude)
+    u0_dev = torch.from_numpy(u0).cuda()
+    solver = kg.Solver(n, dt, blowup_threshold=1e3)
+    solver.set_state(u0_dev)
+    E0, _ = solver.energy()
+
+    st, _ = solver.step(args.warmup, sync=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, _ = kg.kg_step(solver.plan, args.steps, 0)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    done, blown, _ = solver.stats()
+    if blown:
+        raise RuntimeError("the benchmark run blew up")
+
+    # energy every `energy_every` levels of the run so far (E^{m+1/2} from the records)
+    total = done
+    elin, q4, _ = solver.records(0, total)
+    E_series = [(m, float(elin[m] - (q4[m] + q4[m + 1]) / 8.0))
+                for m in range(0, total - 1, args.energy_every)]
+    E_end, _ = solver.energy()
+    for m, e in E_series:
+        print(f"step {m:5d}  E^(m+1/2) = {e:.15e}", file=sys.stderr)
+    drift = abs(E_end - E0) / abs(E0)
+
+    # per-kernel durations, HIP events around every launch of timed steps
+    st, _ = kg.kg_step(solver.plan, args.steps, kg.KG_STEP_TIMED)
+    ms, nt = kg.kg_kernel_times(solver.plan)
+    zi = kg.KERNELS.index("z_update")
+    zbytes = kg.kg_kernel_bytes(solver.plan, zi)
+    z_gbs = zbytes / (ms[zi] * 1e-3) / 1e9
+    kernels = {name: {"ms": ms[i], "GB/s": (kg.kg_kernel_bytes(solver.plan, i) / (ms[i] * 1e-3) / 1e9
+                                            if i < 4 and ms[i] > 0 else None)}
+               for i, name in enumerate(kg.KERNELS)}
+    solver.close()
+
+    steps_per_s = args.steps / elapsed
+    sweep = n * n * (n // 2 + 1) * 16
+    step_bytes = 11 * sweep
+    line = {
+        "metric": "512^3 time steps/s (FP64)" if n == 512 else f"{n}^3 time steps/s (FP64)",
+        "value": steps_per_s,
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"KG {n}^3 FP64 Gaussian A={args.amplitude} sigma=1 "
+                               f"box [-4pi,4pi)^3 dt={dt}", "grid": n, "dt": dt,
+                   "precision": "fp64"},
+        "roofline": {"bound": "hbm", "kernel": "z_update", "achieved": z_gbs,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": z_gbs / HBM_PEAK_GBS,
+                     "traffic": traffic_from_profiles(n),
+                     "algorithmic_bytes_per_launch": zbytes, "avg_launch_ms": ms[zi]},
+        "step_model_GBs": step_bytes / (elapsed / args.steps) / 1e9,
+        "step_hbm_frac": step_bytes / (elapsed / args.steps) / 1e9 / HBM_PEAK_GBS,
+        "kernels": kernels,
+        "energy_drift": drift,
+    }
+    if not args.no_cpu_baseline and n <= 512:
+        line["cpu_baseline"] = cpu_baseline(u0, dt)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,212 @@
+/*
+ * kg.h -- C interface of the MI355X (gfx950) Klein-Gordon spectral stepper.
+ *
+ * The library advances the real cubic Klein-Gordon equation
+ *     u_tt - Lap(u) + u = u^3                     (Sec. 1, eq. (1), real u)
+ * on the periodic box [-L/2, L/2)^3 with n^3 grid points, using the
+ * second-order semi-implicit scheme of Sec. 1.1.2, eq. (2):
+ *     (u^{n+1} - 2u^n + u^{n-1})/dt^2 - Lap (u^{n+1} + 2u^n + u^{n-1})/4
+ *         + (u^{n+1} + 2u^n + u^{n-1})/4 = (u^n)^3,
+ * time-stepped in Fourier space with the cubic term formed in physical
+ * space, two 3D FFTs per step (Sec. 1.1.2, closing paragraph).  Each Fourier
+ * mode k obeys v^{n+1} = alpha_k v^n - v^{n-1} + beta_k F[(u^n)^3] with
+ * a_k = (1 + |k|^2) dt^2 / 4, alpha_k = 2(1 - a_k)/(1 + a_k), beta_k = dt^2/(1 + a_k).
+ * The conserved energy of Sec. 1.1 is evaluated in double precision as a
+ * correctness and fault check.
+ *
+ * Every step runs in the library's own HIP kernels on one GPU: no vendor
+ * FFT.  Work is enqueued on the stream given to kg_plan.
+ *
+ * Conventions.
+ *   - Real fields are double arrays of n*n*n values in [z][y][x] order, x
+ *     fastest; grid point j along an axis sits at x_j = -L/2 + j*L/n.
+ *   - Forward transforms are unnormalised with exp(-2 pi i j k / n); spectra
+ *     returned by kg_get_spectrum are the half spectrum kx = 0..n/2 of the
+ *     full 3D DFT, complex (re, im) doubles in [kz][ky][kx] order with
+ *     n/2+1 values per kx row.
+ *   - "on_device" pointers are device addresses usable on the plan's device;
+ *     otherwise host addresses.  The caller owns every buffer it passes.
+ *   - A plan is not thread-safe; separate plans are independent.
+ *
+ * Errors: every call returns a kg_status; no C++ exception crosses this
+ * interface.  After KG_E_HIP, kg_last_error(plan) holds the HIP message.
+ */
+#ifndef KG_H
+#define KG_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    KG_OK = 0,
+    KG_E_INVALID = 1,          /* bad argument or call order */
+    KG_E_UNSUPPORTED_SIZE = 2, /* n not a supported grid size */
+    KG_E_NOMEM = 3,            /* workspace too small or allocation failed */
+    KG_E_HIP = 4,              /* HIP runtime error */
+    KG_BLOWUP = 5              /* max|u| exceeded the threshold or became non-finite */
+} kg_status;
+
+enum { KG_FP64 = 0, KG_FP32 = 1 };
+enum { KG_INIT_VELOCITY = 0, KG_INIT_TWO_LEVEL = 1 };
+enum { KG_STEP_SYNC = 1u, KG_STEP_TIMED = 2u };
+
+typedef struct {
+    int n;                   /* grid points per axis: a power of two, 8..512 */
+    double L;                /* box length per axis; <= 0 selects 8*pi */
+    double dt;               /* time step, > 0 */
+    int precision;           /* KG_FP64; KG_FP32 is reserved (KG_E_INVALID) */
+    int linear_only;         /* nonzero drops the cubic term (linear KG equation) */
+    double blowup_threshold; /* max|u| above this is a blow-up; <= 0 disables the test */
+} kg_params;
+
+typedef struct kg_plan_s kg_plan_t;
+
+/* Human-readable name of a status code (static storage). */
+const char *kg_status_str(kg_status s);
+
+/* Last error message recorded on a plan (static storage of the plan). */
+const char *kg_last_error(const kg_plan_t *plan);
+
+/*
+ * Device workspace a plan needs, in bytes (0 for invalid parameters).  It
+ * holds the working field (the half spectrum between passes), the two time
+ * levels of eq. (2), the twiddle table and the reduction partials.
+ */
+size_t kg_workspace_bytes(const kg_params *p);
+
+/*
+ * Create a plan.  d_workspace: device buffer of at least
+ * kg_workspace_bytes(p) bytes, borrowed (it must outlive the plan), or NULL
+ * to let the library allocate and own it.  hip_stream: the hipStream_t all
+ * work is enqueued on (NULL = default stream).  No kernel runs.
+ * Errors: KG_E_INVALID (NULL arguments, dt <= 0), KG_E_UNSUPPORTED_SIZE,
+ * KG_E_NOMEM (ws_bytes too small or allocation failure), KG_E_HIP.
+ */
+kg_status kg_plan(const kg_params *p, void *d_workspace, size_t ws_bytes, void *hip_stream,
+                  kg_plan_t **out);
+
+/* Release a plan and anything the library allocated for it (NULL is a no-op). */
+void kg_destroy(kg_plan_t *plan);
+
+/*
+ * Set the initial data and reset the step counter to 0.
+ *   mode KG_INIT_VELOCITY: u0 = u(0), aux = u_t(0) (NULL means zero).  The
+ *     second level eq. (2) needs is the symmetric start
+ *     v^{-1} = (alpha/2) v^0 - dt F[u_t(0)] + (beta/2) F[u0^3],
+ *     so that (v^1 - v^{-1})/(2 dt) = F[u_t(0)] (the paper leaves the start open).
+ *   mode KG_INIT_TWO_LEVEL: u0 = u^0, aux = u^{-1} (required).
+ * Inputs are copied; they may be released after the call returns.
+ * Also evaluates the energy of the initial pair (see kg_energy).
+ */
+kg_status kg_set_state(kg_plan_t *plan, const double *u0, const double *aux, int mode,
+                       int on_device);
+
+/*
+ * Enqueue nsteps steps of eq. (2).  Asynchronous unless flags has
+ * KG_STEP_SYNC.  After each step the max|u^n| of the level just used is
+ * checked; on a blow-up the remaining kernels return at once and the
+ * counter stops at the blown level n.  With KG_STEP_SYNC the call
+ * synchronises, stores the step counter in *steps_done (may be NULL) and
+ * returns KG_BLOWUP if the run has blown up.  With KG_STEP_TIMED every kernel
+ * launch of the call is bracketed by HIP events on the plan's stream and the
+ * call synchronises; kg_kernel_times then reports the per-kernel averages.
+ */
+kg_status kg_step(kg_plan_t *plan, int nsteps, unsigned flags, int *steps_done);
+
+/*
+ * Average duration in milliseconds of each kernel of a step over the last
+ * kg_step call made with KG_STEP_TIMED: ms[0] x pass, ms[1] forward y,
+ * ms[2] z pass with the update, ms[3] inverse y, ms[4] finalize.
+ * *nsteps (may be NULL) = the number of steps averaged (0 if none).
+ */
+kg_status kg_kernel_times(const kg_plan_t *plan, double ms[5], int *nsteps);
+
+/*
+ * Energy of Sec. 1.1 of the newest level pair (v^{n-1}, v^n), n = steps done:
+ *   E^{n-1/2} = (h^3/(2M)) sum_k [|v^n - v^{n-1}|^2/dt^2 + (1+|k|^2)|v^n + v^{n-1}|^2/4]
+ *               - chi (Q4^{n-1} + Q4^n) / 8,   Q4^m = h^3 sum_j (u^m_j)^4,
+ * (M = n^3, h = L/n, chi = 0 for the linear equation), at time t = (n - 1/2) dt.
+ * Synchronises the stream.  E or t may be NULL.
+ */
+kg_status kg_energy(kg_plan_t *plan, double *E, double *t);
+
+/*
+ * Per-step records for levels first..first+count-1 (each level m < steps
+ * done): elin[m] = linear energy of (v^m, v^{m+1}), q4[m] = Q4^m,
+ * maxu[m] = max_j |u^m_j|.  Any output may be NULL.  Synchronises.  Only
+ * the last 65536 levels are retained; older ones give KG_E_INVALID.
+ */
+kg_status kg_records(kg_plan_t *plan, int first, int count, double *elin, double *q4,
+                     double *maxu);
+
+/* Steps done, blow-up flag and blown level (-1 if none).  Synchronises. */
+kg_status kg_stats(kg_plan_t *plan, int *steps_done, int *blown_up, int *blowup_step);
+
+/* u^n (n = steps done) in physical space, n^3 doubles.  Off the hot path. */
+kg_status kg_get_u(kg_plan_t *plan, double *u_out, int on_device);
+
+/*
+ * Spectrum of a stored level: which = 0 gives v^n, which = 1 gives v^{n-1}
+ * (n = steps done), as the half spectrum described above (n*n*(n/2+1)
+ * complex values, 2 doubles each).
+ */
+kg_status kg_get_spectrum(kg_plan_t *plan, int which, double *out, int on_device);
+
+/* Raw state (both levels, step counter): size, save and bitwise resume. */
+size_t kg_state_bytes(const kg_plan_t *plan);
+kg_status kg_save_state(kg_plan_t *plan, void *host_buf, size_t bytes);
+kg_status kg_load_state(kg_plan_t *plan, const void *host_buf, size_t bytes);
+
+/* ------------------------------------------------------------------------ */
+/* Test and measurement hooks (not needed to run the solver).               */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Full forward 3D r2c transform of a real field through the solver's own
+ * kernels (x r2c, y, z): half spectrum as in kg_get_spectrum.  The solver
+ * state is clobbered (call kg_set_state afterwards).
+ */
+kg_status kg_debug_forward(kg_plan_t *plan, const double *u, double *spec, int on_device);
+
+/*
+ * Full inverse 3D c2r transform (z, y, x c2r), unnormalised: returns
+ * Re sum_k X_k exp(+2 pi i k.j / n) over the Hermitian completion of the
+ * given half spectrum.  Clobbers the solver state.
+ */
+kg_status kg_debug_inverse(kg_plan_t *plan, const double *spec, double *u, int on_device);
+
+/*
+ * One pass on a half spectrum in [z][y][kx] order (n/2+1 values per row):
+ * pass 1 = forward c2c along y, 2 = inverse along y, 3 = forward along z,
+ * 4 = inverse along z.  In place on `spec`.  Clobbers the solver state.
+ */
+kg_status kg_debug_pass(kg_plan_t *plan, int pass, double *spec, int on_device);
+
+/*
+ * Average duration, in milliseconds, of `reps` back-to-back launches of one
+ * kernel of the step (kernel 0 = x pass, 1 = forward y, 2 = z pass with the
+ * update, 3 = inverse y), timed with HIP events on the plan's stream.  The
+ * kernels are run on the current state as in a step but the time-level
+ * buffers are not swapped; call kg_set_state before stepping again.
+ */
+kg_status kg_debug_time_kernel(kg_plan_t *plan, int kernel, int reps, float *ms);
+
+/*
+ * Device-to-device copy of `bytes` bytes by the library's plain copy kernel
+ * (reads and writes each byte once), timed over `reps` launches; used to
+ * calibrate bandwidth counters.  *ms = average milliseconds per launch.
+ */
+kg_status kg_debug_copy(void *d_dst, const void *d_src, size_t bytes, int reps, void *hip_stream,
+                        float *ms);
+
+/* Algorithmic HBM bytes one launch of a step kernel moves (see kg_debug_time_kernel). */
+double kg_kernel_bytes(const kg_plan_t *plan, int kernel);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KG_H */

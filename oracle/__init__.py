@@ -32,12 +32,14 @@ class Oracle:
         lib.kgo_fft3d_axis.argtypes = [ctypes.c_int] * 3 + [dp, ctypes.c_int, ctypes.c_int]
         lib.kgo_run.argtypes = ([ctypes.c_int] * 3 + [ctypes.c_double] * 4 +
                                 [ctypes.c_int, ctypes.c_double, ctypes.c_int, dp, dp,
-                                 ctypes.c_int, dp, dp, dp, dp, dp, ip])
+                                 ctypes.c_int, dp, dp, dp, dp, dp, ip, dp])
         lib.kgo_state.argtypes = ([ctypes.c_int] * 3 + [ctypes.c_double] * 4 +
                                   [ctypes.c_int, ctypes.c_int, dp, dp, ctypes.c_int, dp, dp])
+        lib.kgo_first_step_modes.argtypes = ([ctypes.c_int] * 3 + [ctypes.c_double] * 4 +
+                                             [ctypes.c_int, dp, ctypes.c_int, ip, dp, dp])
         lib.kgo_num_threads.argtypes = []
         for f in (lib.kgo_fft1d, lib.kgo_fft3d, lib.kgo_fft3d_axis, lib.kgo_run, lib.kgo_state,
-                  lib.kgo_num_threads):
+                  lib.kgo_first_step_modes, lib.kgo_num_threads):
             f.restype = ctypes.c_int
         self.lib = lib
 
@@ -71,8 +73,9 @@ class Oracle:
         """Step eq. (2) ``nsteps`` times from ``u0`` (and ``aux`` = u_t(0) or u^{-1}).
 
         Returns a dict with ``u`` (u^nsteps or the blown-up level), ``u_prev``,
-        ``energy`` (E^{-1/2}, E^{1/2}, ...), ``maxu`` and ``q4`` per level and
-        ``blowup_step`` (-1 if none).  ``L`` is (Lx, Ly, Lz).
+        ``energy`` (E^{-1/2}, E^{1/2}, ...), ``maxu`` and ``q4`` per level,
+        ``blowup_step`` (-1 if none) and ``loop_seconds`` (wall time of the
+        steps without set-up).  ``L`` is (Lx, Ly, Lz).
         """
         u0 = np.ascontiguousarray(u0, dtype=np.float64)
         nz, ny, nx = u0.shape
@@ -85,11 +88,13 @@ class Oracle:
         maxu = np.empty(nsteps + 1)
         q4 = np.empty(nsteps + 1)
         blow = ctypes.c_int(-1)
+        secs = ctypes.c_double(0.0)
         _check(self.lib.kgo_run(nx, ny, nz, L[0], L[1], L[2], dt, int(bool(linear_only)),
                                 float(threshold), mode, _ptr(u0), _ptr(aux), nsteps, _ptr(u),
                                 _ptr(up), _ptr(energy), _ptr(maxu), _ptr(q4),
-                                ctypes.byref(blow)), "run")
-        return dict(u=u, u_prev=up, energy=energy, maxu=maxu, q4=q4, blowup_step=blow.value)
+                                ctypes.byref(blow), ctypes.byref(secs)), "run")
+        return dict(u=u, u_prev=up, energy=energy, maxu=maxu, q4=q4, blowup_step=blow.value,
+                    loop_seconds=secs.value)
 
     def state(self, u0, dt, nsteps, L=(8 * np.pi,) * 3, linear_only=False, mode=INIT_VELOCITY,
               aux=None):
@@ -104,6 +109,21 @@ class Oracle:
                                   mode, _ptr(u0), _ptr(aux), nsteps, _ptr(vp.view(np.float64)),
                                   _ptr(vc.view(np.float64))), "state")
         return vp, vc
+
+
+    def first_step_modes(self, u0, dt, modes, L=(8 * np.pi,) * 3, linear_only=False):
+        """(v^0, v^1) at the given mode index triples (ix, iy, iz), u_t(0) = 0,
+        each by direct summation of the DFT definition."""
+        u0 = np.ascontiguousarray(u0, dtype=np.float64)
+        nz, ny, nx = u0.shape
+        m = np.ascontiguousarray(np.asarray(modes, dtype=np.int32).reshape(-1, 3))
+        v0 = np.empty(len(m), np.complex128)
+        v1 = np.empty(len(m), np.complex128)
+        _check(self.lib.kgo_first_step_modes(
+            nx, ny, nz, L[0], L[1], L[2], dt, int(bool(linear_only)), _ptr(u0), len(m),
+            m.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _ptr(v0.view(np.float64)),
+            _ptr(v1.view(np.float64))), "first_step_modes")
+        return v0, v1
 
 
 def _ptr(a):
@@ -152,3 +172,7 @@ def run(*args, **kw):
 
 def state(*args, **kw):
     return default().state(*args, **kw)
+
+
+def first_step_modes(*args, **kw):
+    return default().first_step_modes(*args, **kw)

@@ -32,6 +32,7 @@
 #include <stddef.h>
 #include <stdlib.h>
 #include <string.h>
+#include <time.h>
 #ifdef _OPENMP
 #include <omp.h>
 #endif
@@ -402,14 +403,25 @@ static int check_args(int nx, int ny, int nz, double Lx, double Ly, double Lz, d
  *   u_out     = u^{nsteps}, or the level at which blow-up was detected;
  *   uprev_out = the level before u_out;
  *   *blowup_step = first n with max|u^n| > threshold or a non-finite value,
- *                  -1 if none (threshold <= 0 disables the test).
+ *                  -1 if none (threshold <= 0 disables the test);
+ *   *loop_seconds = wall time of the steps themselves (levels 0..nsteps-1:
+ *                  inverse transform, cubic term, forward transform, update),
+ *                  without the set-up and the last level's transform.
  * Any output pointer may be NULL.  Entries after a blow-up stay NaN.
  */
+static double wall_seconds(void)
+{
+    struct timespec ts;
+    clock_gettime(CLOCK_MONOTONIC, &ts);
+    return (double)ts.tv_sec + 1e-9 * (double)ts.tv_nsec;
+}
+
 int kgo_run(int nx, int ny, int nz, double Lx, double Ly, double Lz, double dt,
             int linear_only, double threshold, int mode,
             const double *u0, const double *aux, int nsteps,
             double *u_out, double *uprev_out,
-            double *energy, double *maxu, double *q4, int *blowup_step)
+            double *energy, double *maxu, double *q4, int *blowup_step,
+            double *loop_seconds)
 {
     int rc = check_args(nx, ny, nz, Lx, Ly, Lz, dt, mode, u0, aux, nsteps);
     if (rc != KGO_OK)
@@ -441,6 +453,7 @@ int kgo_run(int nx, int ny, int nz, double Lx, double Ly, double Lz, double dt,
     double q4_prev = st.q4;
     double elin_prev = linear_energy(&g, vp, vc);
 
+    double t0 = wall_seconds(), t1 = t0;
     for (int n = 0; n <= nsteps; n++) {
         /* u^n = Re F^{-1}[v^n] / M; its statistics decide blow-up. */
         if ((rc = physical(&g, vc, w, cube, &st)) != KGO_OK)
@@ -449,6 +462,8 @@ int kgo_run(int nx, int ny, int nz, double Lx, double Ly, double Lz, double dt,
         if (q4) q4[n] = st.q4;
         if (energy) energy[n] = elin_prev - g.chi * (q4_prev + st.q4) / 8.0;
         int is_blown = st.nonfinite || (threshold > 0 && st.maxabs > threshold);
+        if (n == nsteps)
+            t1 = wall_seconds();
         if (is_blown || n == nsteps) {
             if (is_blown) blown = n;
             if (u_out) memcpy(u_out, cube, sizeof(double) * M);
@@ -462,6 +477,8 @@ int kgo_run(int nx, int ny, int nz, double Lx, double Ly, double Lz, double dt,
     }
     if (uprev_out)
         rc = physical(&g, vp, w, uprev_out, &st);
+    if (loop_seconds)
+        *loop_seconds = t1 > t0 ? t1 - t0 : 0.0;
 
 done:
     if (blowup_step) *blowup_step = blown;
@@ -506,4 +523,77 @@ int kgo_state(int nx, int ny, int nz, double Lx, double Ly, double Lz, double dt
 done:
     free(vp); free(vc); free(w); free(cube);
     return rc;
+}
+
+/*
+ * The first step of eq. (2) at selected modes, from u(0) = u0 and u_t(0) = 0,
+ * by direct summation of the DFT definition at each mode k (index triple
+ * (ix, iy, iz), 0 <= i < n per axis):
+ *   v^0_k = sum_j u0_j exp(-2 pi i (ix jx/nx + iy jy/ny + iz jz/nz)),
+ *   N^0_k = chi * (the same sum of u0_j^3),
+ *   v^{-1}_k = (alpha/2) v^0_k + (beta/2) N^0_k     (symmetric start, u_t = 0),
+ *   v^1_k = alpha v^0_k - v^{-1}_k + beta N^0_k.
+ * Lets a solver's output at any grid size be checked mode by mode.
+ * v0_out and v1_out receive 2*nmodes doubles (re, im).
+ */
+int kgo_first_step_modes(int nx, int ny, int nz, double Lx, double Ly, double Lz, double dt,
+                         int linear_only, const double *u0, int nmodes, const int *modes,
+                         double *v0_out, double *v1_out)
+{
+    if (check_args(nx, ny, nz, Lx, Ly, Lz, dt, KGO_INIT_VELOCITY, u0, NULL, 0) != KGO_OK ||
+        nmodes < 0 || (nmodes && (!modes || !v0_out || !v1_out)))
+        return KGO_EINVAL;
+    grid_t g = {nx, ny, nz, Lx, Ly, Lz, dt, linear_only ? 0.0 : 1.0};
+    cplx *ex = (cplx *)malloc(sizeof(cplx) * (size_t)nx);
+    cplx *ey = (cplx *)malloc(sizeof(cplx) * (size_t)ny);
+    cplx *ez = (cplx *)malloc(sizeof(cplx) * (size_t)nz);
+    if (!ex || !ey || !ez) {
+        free(ex); free(ey); free(ez);
+        return KGO_ENOMEM;
+    }
+    for (int q = 0; q < nmodes; q++) {
+        int ix = modes[3 * q], iy = modes[3 * q + 1], iz = modes[3 * q + 2];
+        if (ix < 0 || ix >= nx || iy < 0 || iy >= ny || iz < 0 || iz >= nz) {
+            free(ex); free(ey); free(ez);
+            return KGO_EINVAL;
+        }
+        for (int j = 0; j < nx; j++) {
+            double a = -2.0 * M_PI * (double)(((long)ix * j) % nx) / nx;
+            ex[j] = cos(a) + sin(a) * I;
+        }
+        for (int j = 0; j < ny; j++) {
+            double a = -2.0 * M_PI * (double)(((long)iy * j) % ny) / ny;
+            ey[j] = cos(a) + sin(a) * I;
+        }
+        for (int j = 0; j < nz; j++) {
+            double a = -2.0 * M_PI * (double)(((long)iz * j) % nz) / nz;
+            ez[j] = cos(a) + sin(a) * I;
+        }
+        double r1 = 0, i1 = 0, r3 = 0, i3 = 0;
+#pragma omp parallel for collapse(2) schedule(static) reduction(+ : r1, i1, r3, i3)
+        for (int jz = 0; jz < nz; jz++)
+            for (int jy = 0; jy < ny; jy++) {
+                const double *row = u0 + ((size_t)jz * ny + jy) * nx;
+                cplx s1 = 0, s3 = 0;
+                for (int jx = 0; jx < nx; jx++) {
+                    double u = row[jx];
+                    s1 += u * ex[jx];
+                    s3 += u * u * u * ex[jx];
+                }
+                cplx f = ey[jy] * ez[jz];
+                s1 *= f;
+                s3 *= f;
+                r1 += creal(s1); i1 += cimag(s1);
+                r3 += creal(s3); i3 += cimag(s3);
+            }
+        cplx v0 = r1 + i1 * I, nl = g.chi * (r3 + i3 * I);
+        double al, be;
+        scheme_coeffs(&g, ix, iy, iz, &al, &be);
+        cplx vm1 = 0.5 * al * v0 + 0.5 * be * nl;
+        cplx v1 = al * v0 - vm1 + be * nl;
+        v0_out[2 * q] = creal(v0); v0_out[2 * q + 1] = cimag(v0);
+        v1_out[2 * q] = creal(v1); v1_out[2 * q + 1] = cimag(v1);
+    }
+    free(ex); free(ey); free(ez);
+    return KGO_OK;
 }

@@ -1,0 +1,9 @@
+"""MI355X (gfx950) Fourier pseudo-spectral stepper for the real cubic
+Klein-Gordon equation, eq. (1) with the scheme of eq. (2).
+
+``kg`` is the ctypes binding of the C interface in ``include/kg.h`` (same
+function names); ``Solver`` holds a plan and its torch-allocated workspace.
+"""
+from . import kg
+from .kg import *  # noqa: F401,F403
+from .solver import Solver  # noqa: F401

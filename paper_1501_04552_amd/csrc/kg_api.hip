@@ -1,0 +1,893 @@
+// kg_api.hip -- C-ABI of the Klein-Gordon spectral stepper (declared in kg.h).
+//
+// Host-side plan logic: workspace carving, the initialisation sequence, the
+// step loop (four passes and a finalize per step of eq. (2), Sec. 1.1.2),
+// the energy of Sec. 1.1, checkpointing and the test/measurement hooks.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/kg.h"
+#include "kg_kernels.hpp"
+
+using namespace kg;
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+size_t up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+using Plan = kg_plan_s;
+
+// Kernel launchers for one (precision, grid size, tile width).
+struct Ops {
+    virtual ~Ops() = default;
+    virtual void x(Plan &pl, int mode, const double *rin, double *rout, double chi) = 0;
+    virtual void y(Plan &pl, int dir, bool check_flag) = 0;
+    virtual void z(Plan &pl, int mode, void *Sp, const void *Sc, double scale, int has_vel) = 0;
+    virtual void pair_energy(Plan &pl, const void *S0, const void *S1) = 0;
+    virtual void state_to_spec(Plan &pl, const void *S, double *out) = 0;
+    virtual long x_blocks() const = 0;
+    virtual long z_blocks(int ntx) const = 0;
+};
+
+}  // namespace
+
+struct kg_plan_s {
+    kg_params p{};
+    int n = 0, H = 0, W = 0, ntx = 0, P = 0;
+    double L = 0, h3 = 0, ks2 = 0, invM = 0, escale = 0, chi = 1;
+    size_t esz = 16;
+    hipStream_t stream = nullptr;
+    void *ws = nullptr;
+    bool own_ws = false;
+    size_t ws_bytes = 0;
+    char *Q = nullptr, *S[2] = {nullptr, nullptr}, *tw = nullptr;
+    double *partA = nullptr, *partC = nullptr;
+    Rec *rec = nullptr;
+    Ctl *ctl = nullptr;
+    long nA = 0, nC = 0;
+    size_t q_bytes = 0, s_bytes = 0;
+    long steps = 0;  // steps launched since the state was set
+    bool ready = false;
+    std::unique_ptr<Ops> ops;
+    std::vector<hipEvent_t> tev;  // events of KG_STEP_TIMED calls
+    double kt_ms[5] = {0, 0, 0, 0, 0};
+    int kt_steps = 0;
+    std::string err;
+};
+
+namespace {
+
+constexpr int PAIR_BLOCKS = 1024;
+
+template <typename T, int N, int W>
+struct OpsImpl final : Ops {
+    using YC = YZCfg<N, W>;
+    static long yz_grid(int ntx) { return (long)ntx * ((N + YC::B - 1) / YC::B); }
+
+    long x_blocks() const override { return XCfg<N>::blocks(); }
+    long z_blocks(int ntx) const override { return yz_grid(ntx); }
+
+    void x(Plan &pl, int mode, const double *rin, double *rout, double chi) override
+    {
+        XArgs<T> a;
+        a.Q = (cx<T> *)pl.Q;
+        a.tw = (const cx<T> *)pl.tw;
+        a.rin = rin;
+        a.rout = rout;
+        a.part = pl.partA;
+        a.ctl = pl.ctl;
+        a.P = pl.P;
+        a.chi = (T)chi;
+        dim3 g((unsigned)XCfg<N>::blocks()), b(256);
+        switch (mode) {
+        case X_STEP: hipLaunchKernelGGL((k_xpass<T, N, X_STEP>), g, b, 0, pl.stream, a); break;
+        case X_REDUCE: hipLaunchKernelGGL((k_xpass<T, N, X_REDUCE>), g, b, 0, pl.stream, a); break;
+        case X_R2C: hipLaunchKernelGGL((k_xpass<T, N, X_R2C>), g, b, 0, pl.stream, a); break;
+        case X_C2R: hipLaunchKernelGGL((k_xpass<T, N, X_C2R>), g, b, 0, pl.stream, a); break;
+        }
+    }
+    void y(Plan &pl, int dir, bool check_flag) override
+    {
+        YArgs<T> a;
+        a.Q = (cx<T> *)pl.Q;
+        a.tw = (const cx<T> *)pl.tw;
+        a.ctl = check_flag ? pl.ctl : nullptr;
+        a.P = pl.P;
+        a.H = pl.H;
+        a.ntx = pl.ntx;
+        dim3 g((unsigned)yz_grid(pl.ntx)), b(YC::NT);
+        if (dir < 0)
+            hipLaunchKernelGGL((k_ypass<T, N, W, -1>), g, b, 0, pl.stream, a);
+        else
+            hipLaunchKernelGGL((k_ypass<T, N, W, 1>), g, b, 0, pl.stream, a);
+    }
+    void z(Plan &pl, int mode, void *Sp, const void *Sc, double scale, int has_vel) override
+    {
+        ZArgs<T> a;
+        a.Q = (cx<T> *)pl.Q;
+        a.tw = (const cx<T> *)pl.tw;
+        a.Sp = (cx<T> *)Sp;
+        a.Sc = (const cx<T> *)Sc;
+        a.part = pl.partC;
+        a.ctl = pl.ctl;
+        a.P = pl.P;
+        a.H = pl.H;
+        a.ntx = pl.ntx;
+        a.ks2 = pl.ks2;
+        a.dt = pl.p.dt;
+        a.chi = pl.chi;
+        a.scale = scale;
+        a.has_vel = has_vel;
+        dim3 g((unsigned)yz_grid(pl.ntx)), b(YC::NT);
+        switch (mode) {
+        case Z_STEP: hipLaunchKernelGGL((k_zpass<T, N, W, Z_STEP>), g, b, 0, pl.stream, a); break;
+        case Z_FWD_STATE: hipLaunchKernelGGL((k_zpass<T, N, W, Z_FWD_STATE>), g, b, 0, pl.stream, a); break;
+        case Z_FWD_Q: hipLaunchKernelGGL((k_zpass<T, N, W, Z_FWD_Q>), g, b, 0, pl.stream, a); break;
+        case Z_INV_STATE: hipLaunchKernelGGL((k_zpass<T, N, W, Z_INV_STATE>), g, b, 0, pl.stream, a); break;
+        case Z_INV_Q: hipLaunchKernelGGL((k_zpass<T, N, W, Z_INV_Q>), g, b, 0, pl.stream, a); break;
+        case Z_START: hipLaunchKernelGGL((k_zpass<T, N, W, Z_START>), g, b, 0, pl.stream, a); break;
+        }
+    }
+    void pair_energy(Plan &pl, const void *S0, const void *S1) override
+    {
+        hipLaunchKernelGGL((k_pair_energy<T, N, W>), dim3(PAIR_BLOCKS), dim3(256), 0, pl.stream,
+                           (const cx<T> *)S0, (const cx<T> *)S1, pl.partC, pl.H, pl.ntx, pl.ks2,
+                           pl.p.dt);
+    }
+    void state_to_spec(Plan &pl, const void *S, double *out) override
+    {
+        hipLaunchKernelGGL((k_state_to_spec<T, N, W>), dim3(2048), dim3(256), 0, pl.stream,
+                           (const cx<T> *)S, out, pl.H, pl.ntx);
+    }
+};
+
+// Tile width of the y and z passes: W columns of 16-byte complex values give
+// 64-byte row segments per wavefront load.
+constexpr int W64 = 4;
+
+std::unique_ptr<Ops> make_ops(int n, int precision)
+{
+    if (precision != KG_FP64) return nullptr;
+    switch (n) {
+    case 8: return std::make_unique<OpsImpl<double, 8, W64>>();
+    case 16: return std::make_unique<OpsImpl<double, 16, W64>>();
+    case 32: return std::make_unique<OpsImpl<double, 32, W64>>();
+    case 64: return std::make_unique<OpsImpl<double, 64, W64>>();
+    case 128: return std::make_unique<OpsImpl<double, 128, W64>>();
+    case 256: return std::make_unique<OpsImpl<double, 256, W64>>();
+    case 512: return std::make_unique<OpsImpl<double, 512, W64>>();
+    default: return nullptr;
+    }
+}
+
+bool size_ok(int n) { return n >= 8 && n <= 512 && (n & (n - 1)) == 0; }
+
+struct Layout {
+    int n, H, W, ntx, P;
+    size_t esz, q, s, tw, pa, pc, rec, ctl, total;
+    long nA, nC;
+};
+
+bool layout(const kg_params *p, Layout &lo)
+{
+    if (!p || !size_ok(p->n) || p->precision != KG_FP64) return false;
+    lo.n = p->n;
+    lo.H = p->n / 2 + 1;
+    lo.W = W64;
+    lo.ntx = (lo.H + lo.W - 1) / lo.W;
+    lo.P = lo.ntx * lo.W;
+    lo.esz = 16;
+    auto ops = make_ops(p->n, p->precision);
+    lo.nA = ops->x_blocks();
+    lo.nC = ops->z_blocks(lo.ntx);
+    if (lo.nC < PAIR_BLOCKS) lo.nC = PAIR_BLOCKS;
+    const size_t nn = (size_t)lo.n * lo.n;
+    lo.q = up(nn * lo.P * lo.esz);
+    lo.s = up((size_t)lo.n * lo.ntx * lo.n * lo.W * lo.esz);
+    lo.tw = up((size_t)lo.n * lo.esz);
+    lo.pa = up((size_t)lo.nA * 2 * sizeof(double));
+    lo.pc = up((size_t)lo.nC * 2 * sizeof(double));
+    lo.rec = up((size_t)RING * sizeof(Rec));
+    lo.ctl = up(sizeof(Ctl));
+    lo.total = lo.q + 2 * lo.s + lo.tw + lo.pa + lo.pc + lo.rec + lo.ctl;
+    return true;
+}
+
+kg_status fail(kg_plan_s *pl, kg_status s, const char *msg)
+{
+    if (pl) pl->err = msg;
+    return s;
+}
+
+kg_status hip_fail(kg_plan_s *pl, hipError_t e, const char *where)
+{
+    if (pl) pl->err = std::string(where) + ": " + hipGetErrorString(e);
+    return KG_E_HIP;
+}
+
+#define HIPCHK(pl, expr)                                           \
+    do {                                                           \
+        hipError_t e_ = (expr);                                    \
+        if (e_ != hipSuccess) return hip_fail((pl), e_, #expr);    \
+    } while (0)
+
+#define LAUNCHCHK(pl)                                              \
+    do {                                                           \
+        hipError_t e_ = hipGetLastError();                         \
+        if (e_ != hipSuccess) return hip_fail((pl), e_, "launch"); \
+    } while (0)
+
+Plan &P(kg_plan_s *p) { return *p; }
+
+// Device copy of a real field given on the host or the device.
+struct DevField {
+    double *d = nullptr;
+    bool own = false;
+    ~DevField()
+    {
+        if (own && d) (void)hipFree(d);
+    }
+};
+
+kg_status to_device(kg_plan_s *pl, const double *src, int on_device, DevField &f)
+{
+    if (!src) return KG_OK;
+    if (on_device) {
+        f.d = const_cast<double *>(src);
+        return KG_OK;
+    }
+    const size_t bytes = (size_t)pl->n * pl->n * pl->n * sizeof(double);
+    HIPCHK(pl, hipMalloc((void **)&f.d, bytes));
+    f.own = true;
+    HIPCHK(pl, hipMemcpyAsync(f.d, src, bytes, hipMemcpyHostToDevice, pl->stream));
+    return KG_OK;
+}
+
+// Working field Q (pitch P) <-> half spectrum of doubles (pitch H).
+__global__ void k_q_to_spec(const double2 *Q, double *out, int P, int H, long rows)
+{
+    const long total = rows * H;
+    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < total; i += (long)gridDim.x * 256) {
+        const long r = i / H;
+        const int k = (int)(i % H);
+        const double2 v = Q[r * P + k];
+        out[2 * i] = v.x;
+        out[2 * i + 1] = v.y;
+    }
+}
+__global__ void k_spec_to_q(const double *in, double2 *Q, int P, int H, long rows)
+{
+    const long total = rows * P;
+    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < total; i += (long)gridDim.x * 256) {
+        const long r = i / P;
+        const int k = (int)(i % P);
+        Q[i] = k < H ? make_double2(in[2 * (r * H + k)], in[2 * (r * H + k) + 1]) : make_double2(0, 0);
+    }
+}
+
+// Half spectrum (host or device) -> Q, and back.
+kg_status spec_in(kg_plan_s *pl, const double *spec, int on_device)
+{
+    const size_t bytes = (size_t)pl->n * pl->n * pl->H * 16;
+    double *d = const_cast<double *>(spec);
+    if (!on_device) {
+        HIPCHK(pl, hipMalloc((void **)&d, bytes));
+        HIPCHK(pl, hipMemcpyAsync(d, spec, bytes, hipMemcpyHostToDevice, pl->stream));
+    }
+    hipLaunchKernelGGL(k_spec_to_q, dim3(2048), dim3(256), 0, pl->stream, d, (double2 *)pl->Q,
+                       pl->P, pl->H, (long)pl->n * pl->n);
+    LAUNCHCHK(pl);
+    if (!on_device) {
+        HIPCHK(pl, hipStreamSynchronize(pl->stream));
+        HIPCHK(pl, hipFree(d));
+    }
+    return KG_OK;
+}
+
+kg_status spec_out(kg_plan_s *pl, double *spec, int on_device)
+{
+    const size_t bytes = (size_t)pl->n * pl->n * pl->H * 16;
+    double *d = spec;
+    if (!on_device) HIPCHK(pl, hipMalloc((void **)&d, bytes));
+    hipLaunchKernelGGL(k_q_to_spec, dim3(2048), dim3(256), 0, pl->stream, (const double2 *)pl->Q,
+                       d, pl->P, pl->H, (long)pl->n * pl->n);
+    LAUNCHCHK(pl);
+    if (!on_device) {
+        HIPCHK(pl, hipMemcpyAsync(spec, d, bytes, hipMemcpyDeviceToHost, pl->stream));
+        HIPCHK(pl, hipStreamSynchronize(pl->stream));
+        HIPCHK(pl, hipFree(d));
+    }
+    return KG_OK;
+}
+
+kg_status read_ctl(kg_plan_s *pl, Ctl &c)
+{
+    HIPCHK(pl, hipMemcpyAsync(&c, pl->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, pl->stream));
+    HIPCHK(pl, hipStreamSynchronize(pl->stream));
+    return KG_OK;
+}
+
+// Q <- inverse z and y transforms of level S (scaled by 1/M): what the x pass
+// of the next step expects.
+kg_status prepare_q(kg_plan_s *pl, const void *S)
+{
+    Plan &p = P(pl);
+    p.ops->z(p, Z_INV_STATE, nullptr, S, p.invM, 0);
+    p.ops->y(p, 1, false);
+    LAUNCHCHK(pl);
+    return KG_OK;
+}
+
+// One forward 3D r2c transform of a real field into Q (x, then y; the z
+// transform is done by the caller's z-pass mode).
+void forward_xy(Plan &p, const double *d_real, bool cube)
+{
+    p.ops->x(p, X_R2C, d_real, nullptr, cube ? 1.0 : 0.0);
+    p.ops->y(p, -1, false);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C interface
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+const char *kg_status_str(kg_status s)
+{
+    switch (s) {
+    case KG_OK: return "KG_OK";
+    case KG_E_INVALID: return "KG_E_INVALID";
+    case KG_E_UNSUPPORTED_SIZE: return "KG_E_UNSUPPORTED_SIZE";
+    case KG_E_NOMEM: return "KG_E_NOMEM";
+    case KG_E_HIP: return "KG_E_HIP";
+    case KG_BLOWUP: return "KG_BLOWUP";
+    }
+    return "unknown status";
+}
+
+const char *kg_last_error(const kg_plan_t *plan) { return plan ? plan->err.c_str() : "no plan"; }
+
+size_t kg_workspace_bytes(const kg_params *p)
+{
+    Layout lo;
+    if (!p || !(p->dt > 0)) return 0;
+    return layout(p, lo) ? lo.total : 0;
+}
+
+kg_status kg_plan(const kg_params *p, void *d_workspace, size_t ws_bytes, void *hip_stream,
+                  kg_plan_t **out)
+{
+    if (!p || !out) return KG_E_INVALID;
+    *out = nullptr;
+    if (!(p->dt > 0) || !std::isfinite(p->dt)) return KG_E_INVALID;
+    if (p->precision != KG_FP64 && p->precision != KG_FP32) return KG_E_INVALID;
+    if (p->precision == KG_FP32) return KG_E_INVALID;
+    if (!size_ok(p->n)) return KG_E_UNSUPPORTED_SIZE;
+    Layout lo;
+    if (!layout(p, lo)) return KG_E_INVALID;
+    if (d_workspace && ws_bytes < lo.total) return KG_E_NOMEM;
+
+    kg_plan_s *pl = new (std::nothrow) kg_plan_s();
+    if (!pl) return KG_E_NOMEM;
+    pl->p = *p;
+    pl->n = lo.n;
+    pl->H = lo.H;
+    pl->W = lo.W;
+    pl->ntx = lo.ntx;
+    pl->P = lo.P;
+    pl->esz = lo.esz;
+    pl->L = p->L > 0 ? p->L : 8.0 * M_PI;
+    const double h = pl->L / pl->n;
+    pl->h3 = h * h * h;
+    const double ks = 2.0 * M_PI / pl->L;
+    pl->ks2 = ks * ks;
+    const double M = (double)pl->n * pl->n * pl->n;
+    pl->invM = 1.0 / M;
+    pl->escale = pl->h3 / (2.0 * M);
+    pl->chi = p->linear_only ? 0.0 : 1.0;
+    pl->stream = (hipStream_t)hip_stream;
+    pl->nA = lo.nA;
+    pl->nC = lo.nC;
+    pl->q_bytes = lo.q;
+    pl->s_bytes = lo.s;
+    pl->ops = make_ops(p->n, p->precision);
+
+    if (d_workspace) {
+        pl->ws = d_workspace;
+        pl->ws_bytes = ws_bytes;
+    } else {
+        hipError_t e = hipMalloc(&pl->ws, lo.total);
+        if (e != hipSuccess) {
+            delete pl;
+            return KG_E_NOMEM;
+        }
+        pl->own_ws = true;
+        pl->ws_bytes = lo.total;
+    }
+    char *c = (char *)pl->ws;
+    pl->Q = c;
+    c += lo.q;
+    pl->S[0] = c;
+    c += lo.s;
+    pl->S[1] = c;
+    c += lo.s;
+    pl->tw = c;
+    c += lo.tw;
+    pl->partA = (double *)c;
+    c += lo.pa;
+    pl->partC = (double *)c;
+    c += lo.pc;
+    pl->rec = (Rec *)c;
+    c += lo.rec;
+    pl->ctl = (Ctl *)c;
+
+    // Twiddle table exp(-2 pi i j / n), each entry from cos/sin in double.
+    std::vector<double> tw(2 * (size_t)pl->n);
+    for (int j = 0; j < pl->n; ++j) {
+        const double ang = 2.0 * M_PI * (double)j / (double)pl->n;
+        tw[2 * j] = std::cos(ang);
+        tw[2 * j + 1] = -std::sin(ang);
+    }
+    Ctl c0{};
+    c0.blow_step = -1;
+    hipError_t e = hipMemcpyAsync(pl->tw, tw.data(), tw.size() * sizeof(double),
+                                  hipMemcpyHostToDevice, pl->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(pl->ctl, &c0, sizeof(Ctl), hipMemcpyHostToDevice, pl->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(pl->stream);
+    if (e != hipSuccess) {
+        kg_destroy(pl);
+        return KG_E_HIP;
+    }
+    *out = pl;
+    return KG_OK;
+}
+
+void kg_destroy(kg_plan_t *plan)
+{
+    if (!plan) return;
+    for (hipEvent_t e : plan->tev) (void)hipEventDestroy(e);
+    if (plan->own_ws && plan->ws) (void)hipFree(plan->ws);
+    delete plan;
+}
+
+kg_status kg_set_state(kg_plan_t *plan, const double *u0, const double *aux, int mode,
+                       int on_device)
+{
+    if (!plan || !u0) return KG_E_INVALID;
+    if (mode != KG_INIT_VELOCITY && mode != KG_INIT_TWO_LEVEL)
+        return fail(plan, KG_E_INVALID, "unknown init mode");
+    if (mode == KG_INIT_TWO_LEVEL && !aux)
+        return fail(plan, KG_E_INVALID, "two-level start needs u^{-1}");
+    Plan &p = P(plan);
+    kg_status s;
+    DevField du0, daux;
+    if ((s = to_device(plan, u0, on_device, du0)) != KG_OK) return s;
+    if ((s = to_device(plan, aux, on_device, daux)) != KG_OK) return s;
+
+    Ctl c0{};
+    c0.blow_step = -1;
+    HIPCHK(plan, hipMemcpyAsync(p.ctl, &c0, sizeof(Ctl), hipMemcpyHostToDevice, p.stream));
+    // v^m lives in S[m % 2]: v^0 -> S[0], v^{-1} -> S[1].
+    void *S0 = p.S[0], *S1 = p.S[1];
+    if (mode == KG_INIT_VELOCITY) {
+        if (p.chi != 0.0) {  // N^0 = F[u0^3] -> S1
+            forward_xy(p, du0.d, true);
+            p.ops->z(p, Z_FWD_STATE, S1, nullptr, 1.0, 0);
+        }
+        forward_xy(p, du0.d, false);  // v^0 -> S0
+        p.ops->z(p, Z_FWD_STATE, S0, nullptr, 1.0, 0);
+        if (daux.d) forward_xy(p, daux.d, false);  // F_xy[u_t0] in Q
+        p.ops->z(p, Z_START, S1, S0, 1.0, daux.d ? 1 : 0);
+    } else {
+        forward_xy(p, du0.d, false);
+        p.ops->z(p, Z_FWD_STATE, S0, nullptr, 1.0, 0);
+        forward_xy(p, daux.d, false);
+        p.ops->z(p, Z_FWD_STATE, S1, nullptr, 1.0, 0);
+    }
+    LAUNCHCHK(plan);
+    // Energy of the initial pair: linear part of (v^{-1}, v^0) and Q4 of u^{-1}.
+    p.ops->pair_energy(p, S1, S0);
+    if ((s = prepare_q(plan, S1)) != KG_OK) return s;
+    p.ops->x(p, X_REDUCE, nullptr, nullptr, 0.0);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, p.stream, p.partA, (int)p.nA, p.partC,
+                       PAIR_BLOCKS, p.rec, p.ctl, 0.0, p.escale, p.h3, 2);
+    LAUNCHCHK(plan);
+    if ((s = prepare_q(plan, S0)) != KG_OK) return s;
+    HIPCHK(plan, hipStreamSynchronize(p.stream));
+    p.steps = 0;
+    p.ready = true;
+    return KG_OK;
+}
+
+kg_status kg_step(kg_plan_t *plan, int nsteps, unsigned flags, int *steps_done)
+{
+    if (!plan || nsteps < 0) return KG_E_INVALID;
+    Plan &p = P(plan);
+    if (!p.ready) return fail(plan, KG_E_INVALID, "kg_set_state has not been called");
+    const double thr = p.p.blowup_threshold;
+    const bool timed = (flags & KG_STEP_TIMED) != 0;
+    if (timed) {
+        const size_t need = (size_t)6 * nsteps;
+        while (p.tev.size() < need) {
+            hipEvent_t e;
+            HIPCHK(plan, hipEventCreate(&e));
+            p.tev.push_back(e);
+        }
+    }
+    for (int i = 0; i < nsteps; ++i) {
+        const long m = p.steps + i;
+        void *Sc = p.S[m & 1], *Sp = p.S[(m + 1) & 1];
+        hipEvent_t *ev = timed ? &p.tev[(size_t)6 * i] : nullptr;
+        if (timed) HIPCHK(plan, hipEventRecord(ev[0], p.stream));
+        p.ops->x(p, X_STEP, nullptr, nullptr, p.chi);
+        if (timed) HIPCHK(plan, hipEventRecord(ev[1], p.stream));
+        p.ops->y(p, -1, true);
+        if (timed) HIPCHK(plan, hipEventRecord(ev[2], p.stream));
+        p.ops->z(p, Z_STEP, Sp, Sc, p.invM, 0);
+        if (timed) HIPCHK(plan, hipEventRecord(ev[3], p.stream));
+        p.ops->y(p, 1, true);
+        if (timed) HIPCHK(plan, hipEventRecord(ev[4], p.stream));
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, p.stream, p.partA, (int)p.nA,
+                           p.partC, (int)p.ops->z_blocks(p.ntx), p.rec, p.ctl, thr, p.escale,
+                           p.h3, 0);
+        if (timed) HIPCHK(plan, hipEventRecord(ev[5], p.stream));
+    }
+    LAUNCHCHK(plan);
+    p.steps += nsteps;
+    if (timed) {
+        HIPCHK(plan, hipStreamSynchronize(p.stream));
+        for (int k = 0; k < 5; ++k) p.kt_ms[k] = 0.0;
+        for (int i = 0; i < nsteps; ++i) {
+            for (int k = 0; k < 5; ++k) {
+                float t = 0;
+                HIPCHK(plan, hipEventElapsedTime(&t, p.tev[(size_t)6 * i + k],
+                                                 p.tev[(size_t)6 * i + k + 1]));
+                p.kt_ms[k] += t;
+            }
+        }
+        for (int k = 0; k < 5; ++k) p.kt_ms[k] = nsteps ? p.kt_ms[k] / nsteps : 0.0;
+        p.kt_steps = nsteps;
+    }
+    if (flags & KG_STEP_SYNC) {
+        Ctl c;
+        kg_status s = read_ctl(plan, c);
+        if (s != KG_OK) return s;
+        if (steps_done) *steps_done = c.step;
+        if (c.flag) return KG_BLOWUP;
+    }
+    return KG_OK;
+}
+
+kg_status kg_kernel_times(const kg_plan_t *plan, double ms[5], int *nsteps)
+{
+    if (!plan || !ms) return KG_E_INVALID;
+    for (int k = 0; k < 5; ++k) ms[k] = plan->kt_ms[k];
+    if (nsteps) *nsteps = plan->kt_steps;
+    return KG_OK;
+}
+
+kg_status kg_energy(kg_plan_t *plan, double *E, double *t)
+{
+    if (!plan) return KG_E_INVALID;
+    Plan &p = P(plan);
+    if (!p.ready) return fail(plan, KG_E_INVALID, "kg_set_state has not been called");
+    // Q4 of the newest level from its working field (reductions only).
+    p.ops->x(p, X_REDUCE, nullptr, nullptr, 0.0);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, p.stream, p.partA, (int)p.nA, p.partC,
+                       0, p.rec, p.ctl, 0.0, p.escale, p.h3, 1);
+    LAUNCHCHK(plan);
+    Ctl c;
+    kg_status s = read_ctl(plan, c);
+    if (s != KG_OK) return s;
+    if (c.flag) return KG_BLOWUP;
+    const int n = c.step;
+    Rec r[2];
+    double elin, q4a;
+    if (n == 0) {
+        HIPCHK(plan, hipMemcpy(&r[1], p.rec, sizeof(Rec), hipMemcpyDeviceToHost));
+        elin = c.elin_m;
+        q4a = c.q4_m;
+    } else {
+        HIPCHK(plan, hipMemcpy(&r[0], p.rec + ((n - 1) & (RING - 1)), sizeof(Rec),
+                               hipMemcpyDeviceToHost));
+        HIPCHK(plan, hipMemcpy(&r[1], p.rec + (n & (RING - 1)), sizeof(Rec), hipMemcpyDeviceToHost));
+        elin = r[0].elin;
+        q4a = r[0].q4;
+    }
+    if (E) *E = elin - p.chi * (q4a + r[1].q4) / 8.0;
+    if (t) *t = ((double)n - 0.5) * p.p.dt;
+    return KG_OK;
+}
+
+kg_status kg_records(kg_plan_t *plan, int first, int count, double *elin, double *q4, double *maxu)
+{
+    if (!plan || first < 0 || count < 0) return KG_E_INVALID;
+    Plan &p = P(plan);
+    Ctl c;
+    kg_status s = read_ctl(plan, c);
+    if (s != KG_OK) return s;
+    const int done = c.flag ? c.step + 1 : c.step;  // a blown level has its record too
+    if (first + count > done || done - first > RING)
+        return fail(plan, KG_E_INVALID, "records not available");
+    std::vector<Rec> all(RING);
+    HIPCHK(plan, hipMemcpy(all.data(), p.rec, sizeof(Rec) * RING, hipMemcpyDeviceToHost));
+    for (int i = 0; i < count; ++i) {
+        const Rec &r = all[(first + i) & (RING - 1)];
+        if (elin) elin[i] = r.elin;
+        if (q4) q4[i] = r.q4;
+        if (maxu) maxu[i] = r.maxu;
+    }
+    return KG_OK;
+}
+
+kg_status kg_stats(kg_plan_t *plan, int *steps_done, int *blown_up, int *blowup_step)
+{
+    if (!plan) return KG_E_INVALID;
+    Ctl c;
+    kg_status s = read_ctl(plan, c);
+    if (s != KG_OK) return s;
+    if (steps_done) *steps_done = c.step;
+    if (blown_up) *blown_up = c.flag;
+    if (blowup_step) *blowup_step = c.flag ? c.blow_step : -1;
+    return KG_OK;
+}
+
+kg_status kg_get_u(kg_plan_t *plan, double *u_out, int on_device)
+{
+    if (!plan || !u_out) return KG_E_INVALID;
+    Plan &p = P(plan);
+    if (!p.ready) return fail(plan, KG_E_INVALID, "kg_set_state has not been called");
+    Ctl c;
+    kg_status s = read_ctl(plan, c);
+    if (s != KG_OK) return s;
+    if ((s = prepare_q(plan, p.S[c.step & 1])) != KG_OK) return s;
+    const size_t bytes = (size_t)p.n * p.n * p.n * sizeof(double);
+    double *d = u_out;
+    if (!on_device) HIPCHK(plan, hipMalloc((void **)&d, bytes));
+    p.ops->x(p, X_C2R, nullptr, d, 0.0);
+    LAUNCHCHK(plan);
+    if (!on_device) {
+        HIPCHK(plan, hipMemcpyAsync(u_out, d, bytes, hipMemcpyDeviceToHost, p.stream));
+        HIPCHK(plan, hipStreamSynchronize(p.stream));
+        HIPCHK(plan, hipFree(d));
+    } else {
+        HIPCHK(plan, hipStreamSynchronize(p.stream));
+    }
+    return KG_OK;
+}
+
+kg_status kg_get_spectrum(kg_plan_t *plan, int which, double *out, int on_device)
+{
+    if (!plan || !out || (which != 0 && which != 1)) return KG_E_INVALID;
+    Plan &p = P(plan);
+    if (!p.ready) return fail(plan, KG_E_INVALID, "kg_set_state has not been called");
+    Ctl c;
+    kg_status s = read_ctl(plan, c);
+    if (s != KG_OK) return s;
+    const int level = c.step - which;
+    const void *S = p.S[level & 1];
+    const size_t bytes = (size_t)p.n * p.n * p.H * 16;
+    double *d = out;
+    if (!on_device) HIPCHK(plan, hipMalloc((void **)&d, bytes));
+    p.ops->state_to_spec(p, S, d);
+    LAUNCHCHK(plan);
+    if (!on_device) {
+        HIPCHK(plan, hipMemcpyAsync(out, d, bytes, hipMemcpyDeviceToHost, p.stream));
+        HIPCHK(plan, hipStreamSynchronize(p.stream));
+        HIPCHK(plan, hipFree(d));
+    } else {
+        HIPCHK(plan, hipStreamSynchronize(p.stream));
+    }
+    return KG_OK;
+}
+
+// Saved state: header, both levels, control block and the newest record.
+struct SaveHeader {
+    uint64_t magic;
+    int32_t n, precision, W, pad;
+    double dt, L;
+    int64_t s_bytes;
+};
+static const uint64_t KG_MAGIC = 0x4b47535441544531ull;  // "KGSTATE1"
+
+size_t kg_state_bytes(const kg_plan_t *plan)
+{
+    if (!plan) return 0;
+    return sizeof(SaveHeader) + 2 * plan->s_bytes + sizeof(Ctl) + sizeof(Rec);
+}
+
+kg_status kg_save_state(kg_plan_t *plan, void *host_buf, size_t bytes)
+{
+    if (!plan || !host_buf || bytes < kg_state_bytes(plan)) return KG_E_INVALID;
+    Plan &p = P(plan);
+    if (!p.ready) return fail(plan, KG_E_INVALID, "kg_set_state has not been called");
+    Ctl c;
+    kg_status s = read_ctl(plan, c);
+    if (s != KG_OK) return s;
+    char *b = (char *)host_buf;
+    SaveHeader h{KG_MAGIC, p.n, p.p.precision, p.W, 0, p.p.dt, p.L, (int64_t)p.s_bytes};
+    std::memcpy(b, &h, sizeof h);
+    b += sizeof h;
+    HIPCHK(plan, hipMemcpy(b, p.S[0], p.s_bytes, hipMemcpyDeviceToHost));
+    b += p.s_bytes;
+    HIPCHK(plan, hipMemcpy(b, p.S[1], p.s_bytes, hipMemcpyDeviceToHost));
+    b += p.s_bytes;
+    std::memcpy(b, &c, sizeof c);
+    b += sizeof c;
+    Rec r{};
+    if (c.step > 0)
+        HIPCHK(plan, hipMemcpy(&r, p.rec + ((c.step - 1) & (RING - 1)), sizeof r, hipMemcpyDeviceToHost));
+    std::memcpy(b, &r, sizeof r);
+    return KG_OK;
+}
+
+kg_status kg_load_state(kg_plan_t *plan, const void *host_buf, size_t bytes)
+{
+    if (!plan || !host_buf || bytes < kg_state_bytes(plan)) return KG_E_INVALID;
+    Plan &p = P(plan);
+    const char *b = (const char *)host_buf;
+    SaveHeader h;
+    std::memcpy(&h, b, sizeof h);
+    if (h.magic != KG_MAGIC || h.n != p.n || h.precision != p.p.precision || h.W != p.W ||
+        h.s_bytes != (int64_t)p.s_bytes)
+        return fail(plan, KG_E_INVALID, "saved state does not match this plan");
+    b += sizeof h;
+    HIPCHK(plan, hipMemcpy(p.S[0], b, p.s_bytes, hipMemcpyHostToDevice));
+    b += p.s_bytes;
+    HIPCHK(plan, hipMemcpy(p.S[1], b, p.s_bytes, hipMemcpyHostToDevice));
+    b += p.s_bytes;
+    Ctl c;
+    std::memcpy(&c, b, sizeof c);
+    b += sizeof c;
+    Rec r;
+    std::memcpy(&r, b, sizeof r);
+    HIPCHK(plan, hipMemcpy(p.ctl, &c, sizeof c, hipMemcpyHostToDevice));
+    if (c.step > 0)
+        HIPCHK(plan, hipMemcpy(p.rec + ((c.step - 1) & (RING - 1)), &r, sizeof r, hipMemcpyHostToDevice));
+    kg_status s = prepare_q(plan, p.S[c.step & 1]);
+    if (s != KG_OK) return s;
+    HIPCHK(plan, hipStreamSynchronize(p.stream));
+    p.steps = c.step;
+    p.ready = true;
+    return KG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Test and measurement hooks
+// ---------------------------------------------------------------------------
+
+kg_status kg_debug_forward(kg_plan_t *plan, const double *u, double *spec, int on_device)
+{
+    if (!plan || !u || !spec) return KG_E_INVALID;
+    Plan &p = P(plan);
+    DevField du;
+    kg_status s = to_device(plan, u, on_device, du);
+    if (s != KG_OK) return s;
+    p.ready = false;
+    forward_xy(p, du.d, false);
+    p.ops->z(p, Z_FWD_Q, nullptr, nullptr, 1.0, 0);
+    LAUNCHCHK(plan);
+    s = spec_out(plan, spec, on_device);
+    if (s == KG_OK && on_device) HIPCHK(plan, hipStreamSynchronize(p.stream));
+    return s;
+}
+
+kg_status kg_debug_inverse(kg_plan_t *plan, const double *spec, double *u, int on_device)
+{
+    if (!plan || !u || !spec) return KG_E_INVALID;
+    Plan &p = P(plan);
+    p.ready = false;
+    kg_status s = spec_in(plan, spec, on_device);
+    if (s != KG_OK) return s;
+    p.ops->z(p, Z_INV_Q, nullptr, nullptr, 1.0, 0);
+    p.ops->y(p, 1, false);
+    const size_t bytes = (size_t)p.n * p.n * p.n * sizeof(double);
+    double *d = u;
+    if (!on_device) HIPCHK(plan, hipMalloc((void **)&d, bytes));
+    p.ops->x(p, X_C2R, nullptr, d, 0.0);
+    LAUNCHCHK(plan);
+    if (!on_device) {
+        HIPCHK(plan, hipMemcpyAsync(u, d, bytes, hipMemcpyDeviceToHost, p.stream));
+        HIPCHK(plan, hipStreamSynchronize(p.stream));
+        HIPCHK(plan, hipFree(d));
+    } else {
+        HIPCHK(plan, hipStreamSynchronize(p.stream));
+    }
+    return KG_OK;
+}
+
+kg_status kg_debug_pass(kg_plan_t *plan, int pass, double *spec, int on_device)
+{
+    if (!plan || !spec || pass < 1 || pass > 4) return KG_E_INVALID;
+    Plan &p = P(plan);
+    p.ready = false;
+    kg_status s = spec_in(plan, spec, on_device);
+    if (s != KG_OK) return s;
+    switch (pass) {
+    case 1: p.ops->y(p, -1, false); break;
+    case 2: p.ops->y(p, 1, false); break;
+    case 3: p.ops->z(p, Z_FWD_Q, nullptr, nullptr, 1.0, 0); break;
+    case 4: p.ops->z(p, Z_INV_Q, nullptr, nullptr, 1.0, 0); break;
+    }
+    LAUNCHCHK(plan);
+    s = spec_out(plan, spec, on_device);
+    if (s == KG_OK && on_device) HIPCHK(plan, hipStreamSynchronize(p.stream));
+    return s;
+}
+
+kg_status kg_debug_time_kernel(kg_plan_t *plan, int kernel, int reps, float *ms)
+{
+    if (!plan || !ms || reps < 1 || kernel < 0 || kernel > 3) return KG_E_INVALID;
+    Plan &p = P(plan);
+    if (!p.ready) return fail(plan, KG_E_INVALID, "kg_set_state has not been called");
+    hipEvent_t e0, e1;
+    HIPCHK(plan, hipEventCreate(&e0));
+    HIPCHK(plan, hipEventCreate(&e1));
+    const long m = p.steps;
+    void *Sc = p.S[m & 1], *Sp = p.S[(m + 1) & 1];
+    auto launch = [&]() {
+        switch (kernel) {
+        case 0: p.ops->x(p, X_STEP, nullptr, nullptr, p.chi); break;
+        case 1: p.ops->y(p, -1, true); break;
+        case 2: p.ops->z(p, Z_STEP, Sp, Sc, p.invM, 0); break;
+        case 3: p.ops->y(p, 1, true); break;
+        }
+    };
+    launch();  // warm-up
+    HIPCHK(plan, hipEventRecord(e0, p.stream));
+    for (int i = 0; i < reps; ++i) launch();
+    HIPCHK(plan, hipEventRecord(e1, p.stream));
+    LAUNCHCHK(plan);
+    HIPCHK(plan, hipEventSynchronize(e1));
+    float t = 0;
+    HIPCHK(plan, hipEventElapsedTime(&t, e0, e1));
+    *ms = t / reps;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    p.ready = false;  // the time levels no longer form a valid pair
+    return KG_OK;
+}
+
+kg_status kg_debug_copy(void *d_dst, const void *d_src, size_t bytes, int reps, void *hip_stream,
+                        float *ms)
+{
+    if (!d_dst || !d_src || bytes % 16 || reps < 1 || !ms) return KG_E_INVALID;
+    hipStream_t st = (hipStream_t)hip_stream;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return KG_E_HIP;
+    const long n16 = (long)(bytes / 16);
+    const unsigned grid = 256 * 8 * 4;
+    hipLaunchKernelGGL(k_copy, dim3(grid), dim3(256), 0, st, (uint4 *)d_dst, (const uint4 *)d_src, n16);
+    (void)hipEventRecord(e0, st);
+    for (int i = 0; i < reps; ++i)
+        hipLaunchKernelGGL(k_copy, dim3(grid), dim3(256), 0, st, (uint4 *)d_dst, (const uint4 *)d_src, n16);
+    (void)hipEventRecord(e1, st);
+    if (hipGetLastError() != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return KG_E_HIP;
+    float t = 0;
+    (void)hipEventElapsedTime(&t, e0, e1);
+    *ms = t / reps;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return KG_OK;
+}
+
+double kg_kernel_bytes(const kg_plan_t *plan, int kernel)
+{
+    if (!plan || kernel < 0 || kernel > 3) return 0.0;
+    // one sweep = every half-spectrum value once
+    const double sweep = (double)plan->n * plan->n * plan->H * (double)plan->esz;
+    return kernel == 2 ? 5.0 * sweep : 2.0 * sweep;
+}
+
+}  // extern "C"

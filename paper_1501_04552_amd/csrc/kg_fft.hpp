@@ -1,0 +1,176 @@
+// kg_fft.hpp -- device building blocks of the line FFTs (gfx950).
+//
+// The method needs two 3D FFTs per time step (Sec. 1.1.2, closing paragraph).
+// Each 3D transform is done one axis at a time, every line by a group of
+// threads of one workgroup.  A line of NL points (a power of two) is held as
+// E = min(8, NL) complex values per thread by TPL = NL / E threads; thread t
+// always owns positions {t + j*TPL : j < E}.  The transform is a Stockham
+// decimation-in-time sequence of radix-R stages (R in {2, 4, 8}): stage s
+// with L = product of the earlier radices computes, for butterfly i,
+//     out[(i / L) * L * R + (i % L) + s' * L]
+//         = sum_r w_R^(r s') * ( w_{L R}^(r (i % L)) * in[i + r * NL / R] ),
+// which reads positions {t + j*TPL} in every stage and, in the last stage,
+// also writes them.  Between stages the values go through LDS; the first
+// stage takes them from registers and the last one leaves them in registers,
+// so callers load and store global memory directly in the owned pattern.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace kg {
+
+template <typename T>
+struct alignas(2 * sizeof(T)) cx {
+    T re, im;
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> mk(T a, T b)
+{
+    cx<T> r;
+    r.re = a;
+    r.im = b;
+    return r;
+}
+template <typename T>
+__device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return mk(a.re + b.re, a.im + b.im); }
+template <typename T>
+__device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return mk(a.re - b.re, a.im - b.im); }
+template <typename T>
+__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b)
+{
+    return mk(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re);
+}
+// a * conj(b)
+template <typename T>
+__device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> b)
+{
+    return mk(a.re * b.re + a.im * b.im, a.im * b.re - a.re * b.im);
+}
+template <typename T>
+__device__ __forceinline__ cx<T> conjg(cx<T> a) { return mk(a.re, -a.im); }
+template <typename T>
+__device__ __forceinline__ cx<T> scale(cx<T> a, T s) { return mk(a.re * s, a.im * s); }
+
+// Multiply by -i (DIR = -1, forward) or +i (DIR = +1, inverse).
+template <int DIR, typename T>
+__device__ __forceinline__ cx<T> rot90(cx<T> a)
+{
+    if constexpr (DIR < 0)
+        return mk(a.im, -a.re);
+    else
+        return mk(-a.im, a.re);
+}
+
+// In-place DFT of R values with roots w_R = exp(DIR * 2 pi i / R).
+template <int R, int DIR, typename T>
+__device__ __forceinline__ void dft(cx<T> (&x)[R])
+{
+    if constexpr (R == 2) {
+        cx<T> a = x[0], b = x[1];
+        x[0] = a + b;
+        x[1] = a - b;
+    } else if constexpr (R == 4) {
+        cx<T> y0 = x[0] + x[2], y1 = x[0] - x[2];
+        cx<T> y2 = x[1] + x[3], y3 = rot90<DIR>(x[1] - x[3]);
+        x[0] = y0 + y2;
+        x[2] = y0 - y2;
+        x[1] = y1 + y3;
+        x[3] = y1 - y3;
+    } else if constexpr (R == 8) {
+        // Split into a[r] = x[r] + x[r+4] (even outputs) and
+        // b[r] = (x[r] - x[r+4]) w_8^r (odd outputs), then two DFT-4.
+        const T s = (T)0.70710678118654752440084436210484903928;
+        cx<T> a[4], b[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            a[r] = x[r] + x[r + 4];
+            b[r] = x[r] - x[r + 4];
+        }
+        // w_8^1 = (1 + DIR i)/sqrt2, w_8^2 = DIR i, w_8^3 = (-1 + DIR i)/sqrt2
+        b[1] = mk(s * (b[1].re - (T)DIR * b[1].im), s * (b[1].im + (T)DIR * b[1].re));
+        b[2] = rot90<DIR>(b[2]);
+        b[3] = mk(s * (-b[3].re - (T)DIR * b[3].im), s * (-b[3].im + (T)DIR * b[3].re));
+        dft<4, DIR>(a);
+        dft<4, DIR>(b);
+#pragma unroll
+        for (int s2 = 0; s2 < 4; ++s2) {
+            x[2 * s2] = a[s2];
+            x[2 * s2 + 1] = b[s2];
+        }
+    }
+}
+
+// Radix plan of a line of NL points (power of two, 2 <= NL <= 4096): the first
+// stage takes the remainder radix (2 or 4) when log2(NL) is not a multiple of
+// 3, every other stage is radix 8.
+template <int NL>
+struct Radix {
+    static constexpr int log2n()
+    {
+        int l = 0;
+        while ((1 << l) < NL) ++l;
+        return l;
+    }
+    static constexpr int E = NL >= 8 ? 8 : NL;
+    static constexpr int TPL = NL / E;
+    static constexpr int LG = log2n();
+    static constexpr int REM = LG % 3;  // 0, 1 (radix 2) or 2 (radix 4)
+    static constexpr int NST = LG / 3 + (REM ? 1 : 0);
+    static constexpr int radix(int s) { return (REM && s == 0) ? (1 << REM) : 8; }
+    static constexpr int lbefore(int s)
+    {
+        int l = 1;
+        for (int q = 0; q < s; ++q) l *= radix(q);
+        return l;
+    }
+    static_assert((1 << LG) == NL, "line length must be a power of two");
+};
+
+// Stockham stages S..NST-1 of a line.  v holds the owned positions on entry
+// to stage 0 and on exit from the last stage.  lds points at position 0 of
+// this line in an LDS buffer in which consecutive positions are `ls`
+// elements apart.  tw is the table exp(-2 pi i j / NTAB) with NTAB = NL * twm.
+// Callers must make sure nobody still reads the LDS line when calling.
+template <typename T, int NL, int DIR, int S = 0>
+__device__ __forceinline__ void fft_line(cx<T> (&v)[Radix<NL>::E], cx<T> *lds, int ls, int t,
+                                         const cx<T> *__restrict__ tw, int twm)
+{
+    using P = Radix<NL>;
+    constexpr int E = P::E, TPL = P::TPL;
+    constexpr int R = P::radix(S), L = P::lbefore(S);
+    constexpr bool last = (S == P::NST - 1);
+    if constexpr (S > 0) {
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < E; ++j) v[j] = lds[(t + j * TPL) * ls];
+        if constexpr (!last) __syncthreads();
+    }
+#pragma unroll
+    for (int b = 0; b < E / R; ++b) {
+        const int i = t + TPL * b;
+        const int k = i & (L - 1);
+        cx<T> x[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) x[r] = v[b + r * (E / R)];
+        if constexpr (L > 1) {
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                const cx<T> w = tw[r * k * (NL / (L * R)) * twm];
+                x[r] = (DIR < 0) ? cmul(x[r], w) : cmulc(x[r], w);
+            }
+        }
+        dft<R, DIR>(x);
+        if constexpr (last) {
+#pragma unroll
+            for (int s = 0; s < R; ++s) v[b + s * (E / R)] = x[s];
+        } else {
+            const int base = (i / L) * L * R + k;
+#pragma unroll
+            for (int s = 0; s < R; ++s) lds[(base + s * L) * ls] = x[s];
+        }
+    }
+    if constexpr (!last) fft_line<T, NL, DIR, S + 1>(v, lds, ls, t, tw, twm);
+}
+
+}  // namespace kg

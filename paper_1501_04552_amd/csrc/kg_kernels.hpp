@@ -1,0 +1,513 @@
+// kg_kernels.hpp -- the per-step kernels of the Klein-Gordon stepper (gfx950).
+//
+// One time step of eq. (2) (Sec. 1.1.2) is four passes over the half
+// spectrum plus a one-workgroup finalize:
+//   x pass: per (z, y) line, c2r along x of the working field gives u^n(x);
+//           record max|u| and sum u^4; form chi*u^3; r2c along x.
+//   y pass: per (z, kx) column, forward c2c along y.
+//   z pass: per (ky, kx) column, forward c2c along z gives N^n = F[u^3];
+//           v^{n+1} = alpha v^n - v^{n-1} + beta N^n (eq. (2) per mode);
+//           energy partials of (v^n, v^{n+1}); store v^{n+1}; inverse c2c
+//           along z of v^{n+1}/M.
+//   y pass: inverse c2c along y; the result feeds the next step's x pass.
+// The two 3D FFTs of a step (Sec. 1.1.2, closing paragraph) are thus split
+// over the passes, the inverse one finishing in the next step's x pass.
+//
+// Layouts (element = cx<T>):
+//   Q  working field, [z][y][kx] with kx row pitch P = ntx * W >= n/2+1;
+//   S  a time level, tile-native [ky][tile][kz][W] (tile = kx / W), private
+//      to the z pass so its loads are contiguous per wavefront.
+#pragma once
+
+#include "kg_fft.hpp"
+
+namespace kg {
+
+// Device-side control block and per-level record.
+struct Ctl {
+    int flag;       // nonzero once the run has blown up
+    int step;       // levels completed (the blown level once flag is set)
+    int blow_step;  // level at which blow-up was detected, -1 if none
+    int pad;
+    double elin_m;  // linear energy of the initial pair (v^{-1}, v^0)
+    double q4_m;    // h^3 sum (u^{-1})^4
+    double maxu_m;  // max |u^{-1}|
+    double pad2;
+};
+struct Rec {
+    double elin;  // linear energy of (v^m, v^{m+1})
+    double q4;    // h^3 sum (u^m)^4
+    double maxu;  // max |u^m| (NaN when non-finite)
+    double pad;
+};
+
+constexpr int RING = 65536;  // records kept on the device
+
+// max that keeps a NaN once one is seen
+__device__ __forceinline__ double nanmax(double a, double b)
+{
+    if (a != a) return a;
+    if (b != b) return b;
+    return a > b ? a : b;
+}
+
+// Reduce (max, sum) over a workgroup of NT threads (a power of two) in a
+// fixed order and write the pair to out[0], out[1] from thread 0.  Every
+// thread of the workgroup must call it.
+template <int NT>
+__device__ __forceinline__ void block_max_sum(double mx, double sm, double *out)
+{
+    constexpr int WS = NT < 64 ? NT : 64;  // lanes combined by shuffles
+    constexpr int NW = NT / WS;            // waves
+#pragma unroll
+    for (int off = WS / 2; off > 0; off >>= 1) {
+        mx = nanmax(mx, __shfl_xor(mx, off, WS));
+        sm += __shfl_xor(sm, off, WS);
+    }
+    if constexpr (NW == 1) {
+        if (threadIdx.x == 0) {
+            out[0] = mx;
+            out[1] = sm;
+        }
+    } else {
+        __shared__ double red[2][NW];
+        if ((threadIdx.x & (WS - 1)) == 0) {
+            red[0][threadIdx.x / WS] = mx;
+            red[1][threadIdx.x / WS] = sm;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double m = red[0][0], s = red[1][0];
+            for (int i = 1; i < NW; ++i) {
+                m = nanmax(m, red[0][i]);
+                s += red[1][i];
+            }
+            out[0] = m;
+            out[1] = s;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// x pass
+// ---------------------------------------------------------------------------
+
+enum XMode { X_STEP = 0, X_REDUCE = 1, X_R2C = 2, X_C2R = 3 };
+
+template <typename T>
+struct XArgs {
+    cx<T> *Q;
+    const cx<T> *tw;      // exp(-2 pi i j / n), j < n
+    const double *rin;    // X_R2C: real input [z][y][x]
+    double *rout;         // X_C2R: real output
+    double *part;         // X_STEP / X_REDUCE: (max|u|, sum u^4) per workgroup
+    const Ctl *ctl;
+    int P;                // row pitch of Q
+    T chi;                // cubic coefficient (X_STEP; X_R2C: 1 cubes the input)
+};
+
+template <int N>
+struct XCfg {
+    static constexpr int NH = N / 2;
+    static constexpr int TPL = Radix<NH>::TPL;
+    static constexpr int NT = 256;
+    static constexpr int LPB = NT / TPL;  // lines per workgroup
+    static constexpr int RS = NH + 1;     // LDS row stride
+    static constexpr long blocks() { return ((long)N * N + LPB - 1) / LPB; }
+};
+
+template <typename T, int N, int MODE>
+__global__ __launch_bounds__(256) void k_xpass(XArgs<T> a)
+{
+    using C = XCfg<N>;
+    constexpr int NH = C::NH, E = Radix<NH>::E, TPL = C::TPL, LPB = C::LPB, RS = C::RS;
+    __shared__ cx<T> rows[LPB * RS];
+    if constexpr (MODE == X_STEP || MODE == X_REDUCE) {
+        if (a.ctl->flag) return;
+    }
+    const int t = threadIdx.x % TPL, l = threadIdx.x / TPL;
+    const long line = (long)blockIdx.x * LPB + l;
+    const bool act = line < (long)N * N;
+    cx<T> *r = rows + l * RS;
+    const cx<T> zero = mk<T>(0, 0);
+    cx<T> v[E];
+    double mx = 0.0, s4 = 0.0;
+
+    if constexpr (MODE == X_R2C) {
+        // packed real line: z[m] = x[2m] + i x[2m+1]
+        const double *src = a.rin + line * N;
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+            const int m = t + j * TPL;
+            T x0 = act ? (T)src[2 * m] : (T)0, x1 = act ? (T)src[2 * m + 1] : (T)0;
+            if (a.chi != (T)0) {
+                x0 = x0 * x0 * x0;
+                x1 = x1 * x1 * x1;
+            }
+            v[j] = mk(x0, x1);
+        }
+    } else {
+        cx<T> *q = a.Q + line * a.P;
+        for (int e = t; e < NH + 1; e += TPL) r[e] = act ? q[e] : zero;
+        __syncthreads();
+        // Hermitian half line X[0..NH] -> Z[k] = E[k] + i O[k] with
+        // E[k] = X[k] + conj(X[NH-k]), O[k] = (X[k] - conj(X[NH-k])) e^{+2 pi i k/N};
+        // the imaginary parts of X[0] and X[NH] are dropped (real field).
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+            const int k = t + j * TPL;
+            cx<T> xk = r[k], xm = r[NH - k];
+            if (k == 0) {
+                xk.im = 0;
+                xm.im = 0;
+            }
+            const cx<T> sum = xk + conjg(xm), dif = xk - conjg(xm);
+            v[j] = sum + rot90<1>(cmulc(dif, a.tw[k]));
+        }
+        __syncthreads();
+        fft_line<T, NH, 1>(v, r, 1, t, a.tw, 2);
+        // v[j] = u[2m] + i u[2m+1], m = t + j*TPL
+        if constexpr (MODE == X_C2R) {
+            if (act) {
+                double *dst = a.rout + line * N;
+#pragma unroll
+                for (int j = 0; j < E; ++j) {
+                    const int m = t + j * TPL;
+                    dst[2 * m] = (double)v[j].re;
+                    dst[2 * m + 1] = (double)v[j].im;
+                }
+            }
+            return;
+        }
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+            const double u0 = (double)v[j].re, u1 = (double)v[j].im;
+            if (act) {
+                mx = nanmax(mx, nanmax(fabs(u0), fabs(u1)));
+                s4 += u0 * u0 * u0 * u0 + u1 * u1 * u1 * u1;
+            }
+        }
+        if constexpr (MODE == X_REDUCE) {
+            block_max_sum<256>(mx, s4, a.part + 2 * blockIdx.x);
+            return;
+        }
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+            const T u0 = v[j].re, u1 = v[j].im;
+            v[j] = mk(a.chi * u0 * u0 * u0, a.chi * u1 * u1 * u1);
+        }
+        __syncthreads();
+    }
+    fft_line<T, NH, -1>(v, r, 1, t, a.tw, 2);
+    // Z'[k] -> W[k] = Ev[k] + e^{-2 pi i k/N} Od[k], k = 0..NH, with
+    // Ev = (Z'[k] + conj Z'[NH-k])/2, Od = (Z'[k] - conj Z'[NH-k])/(2i).
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < E; ++j) r[t + j * TPL] = v[j];
+    __syncthreads();
+    if (act) {
+        cx<T> *q = a.Q + line * a.P;
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+            const int k = t + j * TPL;
+            const cx<T> zk = r[k], zm = conjg(r[(NH - k) & (NH - 1)]);
+            const cx<T> ev = scale(zk + zm, (T)0.5);
+            const cx<T> od = scale(rot90<-1>(zk - zm), (T)0.5);
+            q[k] = ev + cmul(od, a.tw[k]);
+            if (k == 0) q[NH] = ev - od;
+        }
+    }
+    if constexpr (MODE == X_STEP) block_max_sum<256>(mx, s4, a.part + 2 * blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// y pass: c2c along y for every (z, kx)
+// ---------------------------------------------------------------------------
+
+template <int N, int W>
+struct YZCfg {
+    static constexpr int TPL = Radix<N>::TPL;
+    static constexpr int B0 = 256 / (W * TPL) > 0 ? 256 / (W * TPL) : 1;
+    static constexpr int B = B0 < N ? B0 : N;  // outer lines per workgroup
+    static constexpr int NT = W * TPL * B;
+};
+
+template <typename T>
+struct YArgs {
+    cx<T> *Q;
+    const cx<T> *tw;
+    const Ctl *ctl;  // NULL: no blow-up test
+    int P, H, ntx;
+};
+
+template <typename T, int N, int W, int DIR>
+__global__ __launch_bounds__((YZCfg<N, W>::NT)) void k_ypass(YArgs<T> a)
+{
+    using C = YZCfg<N, W>;
+    constexpr int E = Radix<N>::E, TPL = C::TPL, B = C::B;
+    __shared__ cx<T> lds[W * B * N];
+    if (a.ctl && a.ctl->flag) return;
+    const int c = threadIdx.x % W, t = (threadIdx.x / W) % TPL, b = threadIdx.x / (W * TPL);
+    const int tile = blockIdx.x % a.ntx, z = (blockIdx.x / a.ntx) * B + b;
+    const int kx = tile * W + c;
+    const bool act = kx < a.H && z < N;
+    cx<T> *g = a.Q + ((long)z * N) * a.P + kx;
+    cx<T> v[E];
+#pragma unroll
+    for (int j = 0; j < E; ++j) v[j] = act ? g[(long)(t + j * TPL) * a.P] : mk<T>(0, 0);
+    fft_line<T, N, DIR>(v, lds + c + W * b, W * B, t, a.tw, 1);
+    if (act) {
+#pragma unroll
+        for (int j = 0; j < E; ++j) g[(long)(t + j * TPL) * a.P] = v[j];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// z pass: c2c along z, with the eq. (2) update on the hot path
+// ---------------------------------------------------------------------------
+
+enum ZMode {
+    Z_STEP = 0,       // forward z, update, energy, store v^{n+1}, inverse z of v^{n+1}/M
+    Z_FWD_STATE = 1,  // forward z -> state buffer
+    Z_FWD_Q = 2,      // forward z in place
+    Z_INV_STATE = 3,  // state buffer * scale -> inverse z -> Q
+    Z_INV_Q = 4,      // inverse z in place, times scale
+    Z_START = 5       // symmetric start: Sp = (alpha/2) Sc - dt Fz(Q) + (beta/2) chi Sp
+};
+
+template <typename T>
+struct ZArgs {
+    cx<T> *Q;
+    const cx<T> *tw;
+    cx<T> *Sp;        // Z_STEP: v^{n-1} in, v^{n+1} out; Z_FWD_STATE: output; Z_START: N^0 in, v^{-1} out
+    const cx<T> *Sc;  // Z_STEP / Z_START: v^n; Z_INV_STATE: input level
+    double *part;     // Z_STEP: energy partial per workgroup
+    const Ctl *ctl;
+    int P, H, ntx;
+    double ks2;       // (2 pi / L)^2
+    double dt;
+    double chi;
+    double scale;     // 1/M for Z_STEP and Z_INV_STATE
+    int has_vel;      // Z_START: Q holds F_xy[u_t0]
+};
+
+// alpha, beta of eq. (2) and omega^2 for mode numbers (mx, my, mz).
+__device__ __forceinline__ void coeffs(int mx, int my, int mz, double ks2, double dt, double &al,
+                                       double &be, double &w2)
+{
+    w2 = 1.0 + ks2 * (double)(mx * mx + my * my + mz * mz);
+    const double a = 0.25 * w2 * dt * dt;
+    const double inv = 1.0 / (1.0 + a);
+    al = 2.0 * (1.0 - a) * inv;
+    be = dt * dt * inv;
+}
+
+template <typename T, int N, int W, int MODE>
+__global__ __launch_bounds__((YZCfg<N, W>::NT)) void k_zpass(ZArgs<T> a)
+{
+    using C = YZCfg<N, W>;
+    constexpr int E = Radix<N>::E, TPL = C::TPL, B = C::B, NT = C::NT;
+    __shared__ cx<T> lds[W * B * N];
+    if constexpr (MODE == Z_STEP) {
+        if (a.ctl->flag) return;
+    }
+    const int c = threadIdx.x % W, t = (threadIdx.x / W) % TPL, b = threadIdx.x / (W * TPL);
+    const int tile = blockIdx.x % a.ntx, ky = (blockIdx.x / a.ntx) * B + b;
+    const int kx = tile * W + c;
+    const bool act = kx < a.H && ky < N;
+    const long zs = (long)N * a.P;
+    cx<T> *g = a.Q + (long)ky * a.P + kx;
+    const long sbase = (((long)(ky < N ? ky : 0) * a.ntx + tile) * N) * W + c;
+    cx<T> *lline = lds + c + W * b;
+    const cx<T> zero = mk<T>(0, 0);
+    cx<T> v[E];
+
+    if constexpr (MODE == Z_STEP || MODE == Z_FWD_STATE || MODE == Z_FWD_Q || MODE == Z_START) {
+        if (MODE != Z_START || a.has_vel) {
+#pragma unroll
+            for (int j = 0; j < E; ++j) v[j] = act ? g[(t + j * TPL) * zs] : zero;
+            fft_line<T, N, -1>(v, lline, W * B, t, a.tw, 1);
+        } else {
+#pragma unroll
+            for (int j = 0; j < E; ++j) v[j] = zero;
+        }
+    }
+    if constexpr (MODE == Z_FWD_Q) {
+        if (act) {
+#pragma unroll
+            for (int j = 0; j < E; ++j) g[(t + j * TPL) * zs] = v[j];
+        }
+        return;
+    }
+    if constexpr (MODE == Z_FWD_STATE) {
+        if (act) {
+#pragma unroll
+            for (int j = 0; j < E; ++j) a.Sp[sbase + (long)(t + j * TPL) * W] = v[j];
+        }
+        return;
+    }
+    const int my = ky <= N / 2 ? ky : ky - N;
+    if constexpr (MODE == Z_START) {
+        if (act) {
+#pragma unroll
+            for (int j = 0; j < E; ++j) {
+                const int kz = t + j * TPL, mz = kz <= N / 2 ? kz : kz - N;
+                double al, be, w2;
+                coeffs(kx, my, mz, a.ks2, a.dt, al, be, w2);
+                const long si = sbase + (long)kz * W;
+                const cx<T> vc = a.Sc[si];
+                const cx<T> nl = a.chi != 0.0 ? a.Sp[si] : zero;
+                const double re = 0.5 * al * (double)vc.re - a.dt * (double)v[j].re +
+                                  0.5 * be * a.chi * (double)nl.re;
+                const double im = 0.5 * al * (double)vc.im - a.dt * (double)v[j].im +
+                                  0.5 * be * a.chi * (double)nl.im;
+                a.Sp[si] = mk((T)re, (T)im);
+            }
+        }
+        return;
+    }
+    double esum = 0.0;
+    if constexpr (MODE == Z_STEP) {
+        const double wgt = (kx == 0 || kx == N / 2) ? 1.0 : 2.0;
+        const double idt2 = 1.0 / (a.dt * a.dt);
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+            const int kz = t + j * TPL, mz = kz <= N / 2 ? kz : kz - N;
+            cx<T> nv = zero;
+            if (act) {
+                double al, be, w2;
+                coeffs(kx, my, mz, a.ks2, a.dt, al, be, w2);
+                const long si = sbase + (long)kz * W;
+                const cx<T> vc = a.Sc[si], vp = a.Sp[si];
+                const double re = al * (double)vc.re - (double)vp.re + be * (double)v[j].re;
+                const double im = al * (double)vc.im - (double)vp.im + be * (double)v[j].im;
+                nv = mk((T)re, (T)im);
+                a.Sp[si] = nv;
+                const double dr = (double)nv.re - (double)vc.re, di = (double)nv.im - (double)vc.im;
+                const double sr = (double)nv.re + (double)vc.re, sim = (double)nv.im + (double)vc.im;
+                esum += wgt * ((dr * dr + di * di) * idt2 + 0.25 * w2 * (sr * sr + sim * sim));
+            }
+            v[j] = scale(nv, (T)a.scale);
+        }
+        __syncthreads();
+    } else if constexpr (MODE == Z_INV_STATE) {
+#pragma unroll
+        for (int j = 0; j < E; ++j)
+            v[j] = act ? scale(a.Sc[sbase + (long)(t + j * TPL) * W], (T)a.scale) : zero;
+    } else if constexpr (MODE == Z_INV_Q) {
+#pragma unroll
+        for (int j = 0; j < E; ++j) v[j] = act ? scale(g[(t + j * TPL) * zs], (T)a.scale) : zero;
+        __syncthreads();
+    }
+    fft_line<T, N, 1>(v, lline, W * B, t, a.tw, 1);
+    if (act) {
+#pragma unroll
+        for (int j = 0; j < E; ++j) g[(t + j * TPL) * zs] = v[j];
+    }
+    if constexpr (MODE == Z_STEP) block_max_sum<NT>(0.0, esum, a.part + 2 * blockIdx.x);
+}
+
+// Linear energy partials of a pair of levels stored in the state layout:
+// sum w_k [|v1 - v0|^2/dt^2 + omega_k^2 |v1 + v0|^2 / 4] (w_k = 1 on the kx = 0
+// and kx = n/2 planes, 2 elsewhere: the half spectrum stands for the full one).
+template <typename T, int N, int W>
+__global__ __launch_bounds__(256) void k_pair_energy(const cx<T> *S0, const cx<T> *S1, double *part,
+                                                     int H, int ntx, double ks2, double dt)
+{
+    const long total = (long)N * ntx * N * W;
+    double esum = 0.0;
+    const double idt2 = 1.0 / (dt * dt);
+    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < total; i += (long)gridDim.x * 256) {
+        const int c = (int)(i % W);
+        const int kz = (int)((i / W) % N);
+        const long rest = i / ((long)W * N);
+        const int tile = (int)(rest % ntx), ky = (int)(rest / ntx);
+        const int kx = tile * W + c;
+        if (kx >= H) continue;
+        const int my = ky <= N / 2 ? ky : ky - N, mz = kz <= N / 2 ? kz : kz - N;
+        double al, be, w2;
+        coeffs(kx, my, mz, ks2, dt, al, be, w2);
+        const double wgt = (kx == 0 || kx == N / 2) ? 1.0 : 2.0;
+        const cx<T> a0 = S0[i], a1 = S1[i];
+        const double dr = (double)a1.re - (double)a0.re, di = (double)a1.im - (double)a0.im;
+        const double sr = (double)a1.re + (double)a0.re, si = (double)a1.im + (double)a0.im;
+        esum += wgt * ((dr * dr + di * di) * idt2 + 0.25 * w2 * (sr * sr + si * si));
+    }
+    block_max_sum<256>(0.0, esum, part + 2 * blockIdx.x);
+}
+
+// Gather a state-layout level into the half-spectrum layout [kz][ky][kx] (pitch H).
+template <typename T, int N, int W>
+__global__ __launch_bounds__(256) void k_state_to_spec(const cx<T> *S, double *out, int H, int ntx)
+{
+    const long total = (long)N * N * H;
+    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < total; i += (long)gridDim.x * 256) {
+        const int kx = (int)(i % H);
+        const int ky = (int)((i / H) % N);
+        const int kz = (int)(i / ((long)H * N));
+        const long si = (((long)ky * ntx + kx / W) * N + kz) * W + (kx % W);
+        out[2 * i] = (double)S[si].re;
+        out[2 * i + 1] = (double)S[si].im;
+    }
+}
+
+// Fixed-order reduction of the workgroup partials of a step.
+//   mode 0 (step):   rec[step] = {elin, q4, maxu}; blow-up test; step counter.
+//   mode 1 (reduce): rec[step].q4/maxu from the x-pass partials only.
+//   mode 2 (init):   ctl->elin_m, q4_m, maxu_m.
+__global__ __launch_bounds__(256) void k_finalize(const double *partA, int nA, const double *partC,
+                                                  int nC, Rec *rec, Ctl *ctl, double thr,
+                                                  double escale, double h3, int mode)
+{
+    if (mode != 2 && ctl->flag) return;
+    double mx = 0.0, s4 = 0.0, se = 0.0;
+    for (int i = threadIdx.x; i < nA; i += 256) {
+        mx = nanmax(mx, partA[2 * i]);
+        s4 += partA[2 * i + 1];
+    }
+    if (mode != 1)
+        for (int i = threadIdx.x; i < nC; i += 256) se += partC[2 * i + 1];
+    __shared__ double red[3][256];
+    red[0][threadIdx.x] = mx;
+    red[1][threadIdx.x] = s4;
+    red[2][threadIdx.x] = se;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            red[0][threadIdx.x] = nanmax(red[0][threadIdx.x], red[0][threadIdx.x + s]);
+            red[1][threadIdx.x] += red[1][threadIdx.x + s];
+            red[2][threadIdx.x] += red[2][threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    const double maxu = red[0][0], q4 = h3 * red[1][0], elin = escale * red[2][0];
+    const bool bad = !(maxu <= 1.7976931348623157e308);  // NaN or inf
+    if (mode == 2) {
+        ctl->elin_m = elin;
+        ctl->q4_m = q4;
+        ctl->maxu_m = bad ? __builtin_nan("") : maxu;
+        return;
+    }
+    const int n = ctl->step;
+    Rec *r = rec + (n & (RING - 1));
+    r->q4 = q4;
+    r->maxu = bad ? __builtin_nan("") : maxu;
+    if (mode == 1) return;
+    r->elin = elin;
+    if (bad || (thr > 0.0 && maxu > thr)) {
+        ctl->flag = 1;
+        ctl->blow_step = n;
+    } else {
+        ctl->step = n + 1;
+    }
+}
+
+// Plain copy (calibration of bandwidth counters): 16 bytes per thread per pass.
+__global__ __launch_bounds__(256) void k_copy(uint4 *dst, const uint4 *src, long n16)
+{
+    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n16; i += (long)gridDim.x * 256)
+        dst[i] = src[i];
+}
+
+}  // namespace kg

@@ -1,0 +1,235 @@
+"""ctypes binding of libkg.so, the HIP (gfx950) Klein-Gordon spectral stepper.
+
+The functions keep the C names of ``include/kg.h`` and only marshal
+arguments; every step of the solver runs in the library's kernels.  PyTorch
+supplies device memory (the workspace, device-resident fields) and the HIP
+stream.  Importing fails loudly when the library has not been built.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from .build import LIB
+
+if not os.path.exists(LIB):
+    raise ImportError(f"{LIB} is missing: build it with `python -m paper_1501_04552_amd.build` "
+                      "or __graft_entry__.build()")
+
+_lib = ctypes.CDLL(LIB)
+
+KG_OK, KG_E_INVALID, KG_E_UNSUPPORTED_SIZE, KG_E_NOMEM, KG_E_HIP, KG_BLOWUP = range(6)
+KG_FP64, KG_FP32 = 0, 1
+KG_INIT_VELOCITY, KG_INIT_TWO_LEVEL = 0, 1
+KG_STEP_SYNC = 1
+KG_STEP_TIMED = 2
+
+# names of the step kernels for kg_debug_time_kernel / kg_kernel_bytes
+KERNELS = ("x_pass", "y_forward", "z_update", "y_inverse", "finalize")
+
+
+class kg_params(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("L", ctypes.c_double), ("dt", ctypes.c_double),
+                ("precision", ctypes.c_int), ("linear_only", ctypes.c_int),
+                ("blowup_threshold", ctypes.c_double)]
+
+
+_vp = ctypes.c_void_p
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int)
+_pp = ctypes.POINTER(ctypes.c_void_p)
+_P = ctypes.POINTER(kg_params)
+
+_SIGS = {
+    "kg_status_str": (ctypes.c_char_p, [ctypes.c_int]),
+    "kg_last_error": (ctypes.c_char_p, [_vp]),
+    "kg_workspace_bytes": (ctypes.c_size_t, [_P]),
+    "kg_plan": (ctypes.c_int, [_P, _vp, ctypes.c_size_t, _vp, _pp]),
+    "kg_destroy": (None, [_vp]),
+    "kg_set_state": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int]),
+    "kg_step": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_uint, _ip]),
+    "kg_energy": (ctypes.c_int, [_vp, _dp, _dp]),
+    "kg_records": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]),
+    "kg_stats": (ctypes.c_int, [_vp, _ip, _ip, _ip]),
+    "kg_get_u": (ctypes.c_int, [_vp, _vp, ctypes.c_int]),
+    "kg_get_spectrum": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.c_int]),
+    "kg_state_bytes": (ctypes.c_size_t, [_vp]),
+    "kg_save_state": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t]),
+    "kg_load_state": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t]),
+    "kg_debug_forward": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int]),
+    "kg_debug_inverse": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int]),
+    "kg_debug_pass": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.c_int]),
+    "kg_debug_time_kernel": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int,
+                                            ctypes.POINTER(ctypes.c_float)]),
+    "kg_debug_copy": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, ctypes.c_int, _vp,
+                                     ctypes.POINTER(ctypes.c_float)]),
+    "kg_kernel_bytes": (ctypes.c_double, [_vp, ctypes.c_int]),
+    "kg_kernel_times": (ctypes.c_int, [_vp, _dp, _ip]),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+EXPORTS = tuple(_SIGS)
+
+
+class KGError(RuntimeError):
+    def __init__(self, status, msg=""):
+        self.status = status
+        super().__init__(f"{kg_status_str(status)}{': ' + msg if msg else ''}")
+
+
+def kg_status_str(status):
+    return _lib.kg_status_str(status).decode()
+
+
+def kg_last_error(plan):
+    return _lib.kg_last_error(plan).decode()
+
+
+def _check(status, plan=None, allow=(KG_OK,)):
+    if status not in allow:
+        raise KGError(status, kg_last_error(plan) if plan else "")
+    return status
+
+
+def make_params(n, dt, L=0.0, precision=KG_FP64, linear_only=False, blowup_threshold=0.0):
+    return kg_params(int(n), float(L), float(dt), int(precision), int(bool(linear_only)),
+                     float(blowup_threshold))
+
+
+def kg_workspace_bytes(params):
+    return _lib.kg_workspace_bytes(ctypes.byref(params))
+
+
+def kg_plan(params, workspace_ptr=None, ws_bytes=0, stream=None):
+    out = ctypes.c_void_p()
+    _check(_lib.kg_plan(ctypes.byref(params), workspace_ptr, ws_bytes, stream, ctypes.byref(out)))
+    return out.value
+
+
+def kg_destroy(plan):
+    _lib.kg_destroy(plan)
+
+
+def _buf(x):
+    """(pointer, on_device) of a numpy array or a torch tensor."""
+    if x is None:
+        return None, 0
+    if isinstance(x, np.ndarray):
+        assert x.flags.c_contiguous and x.dtype == np.float64
+        return x.ctypes.data, 0
+    assert x.is_contiguous() and x.is_cuda
+    return x.data_ptr(), 1
+
+
+def kg_set_state(plan, u0, aux=None, mode=KG_INIT_VELOCITY):
+    p0, d0 = _buf(u0)
+    pa, da = _buf(aux)
+    if aux is not None and da != d0:
+        raise ValueError("u0 and aux must both be host or both be device arrays")
+    _check(_lib.kg_set_state(plan, p0, pa, mode, d0), plan)
+
+
+def kg_step(plan, nsteps, flags=0):
+    done = ctypes.c_int(-1)
+    st = _check(_lib.kg_step(plan, nsteps, flags, ctypes.byref(done)), plan,
+                allow=(KG_OK, KG_BLOWUP))
+    return st, done.value
+
+
+def kg_energy(plan):
+    E, t = ctypes.c_double(), ctypes.c_double()
+    st = _check(_lib.kg_energy(plan, ctypes.byref(E), ctypes.byref(t)), plan,
+                allow=(KG_OK, KG_BLOWUP))
+    return (E.value, t.value) if st == KG_OK else (float("nan"), float("nan"))
+
+
+def kg_records(plan, first, count):
+    elin, q4, maxu = np.empty(count), np.empty(count), np.empty(count)
+    _check(_lib.kg_records(plan, first, count, elin.ctypes.data, q4.ctypes.data,
+                           maxu.ctypes.data), plan)
+    return elin, q4, maxu
+
+
+def kg_stats(plan):
+    s, b, bs = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(_lib.kg_stats(plan, ctypes.byref(s), ctypes.byref(b), ctypes.byref(bs)), plan)
+    return s.value, bool(b.value), bs.value
+
+
+def kg_get_u(plan, n, out=None):
+    if out is None:
+        out = np.empty((n, n, n))
+    p, d = _buf(out)
+    _check(_lib.kg_get_u(plan, p, d), plan)
+    return out
+
+
+def kg_get_spectrum(plan, n, which=0, out=None):
+    """Half spectrum [kz][ky][kx<=n/2] of v^n (which=0) or v^{n-1} (which=1)."""
+    if out is None:
+        out = np.empty((n, n, n // 2 + 1), np.complex128)
+    _check(_lib.kg_get_spectrum(plan, which, out.ctypes.data, 0), plan)
+    return out
+
+
+def kg_state_bytes(plan):
+    return _lib.kg_state_bytes(plan)
+
+
+def kg_save_state(plan):
+    buf = np.empty(kg_state_bytes(plan), np.uint8)
+    _check(_lib.kg_save_state(plan, buf.ctypes.data, buf.size), plan)
+    return buf
+
+
+def kg_load_state(plan, buf):
+    buf = np.ascontiguousarray(buf, np.uint8)
+    _check(_lib.kg_load_state(plan, buf.ctypes.data, buf.size), plan)
+
+
+def kg_debug_forward(plan, u):
+    n = u.shape[0]
+    spec = np.empty((n, n, n // 2 + 1), np.complex128)
+    _check(_lib.kg_debug_forward(plan, u.ctypes.data, spec.ctypes.data, 0), plan)
+    return spec
+
+
+def kg_debug_inverse(plan, spec):
+    n = spec.shape[0]
+    spec = np.ascontiguousarray(spec, np.complex128)
+    u = np.empty((n, n, n))
+    _check(_lib.kg_debug_inverse(plan, spec.ctypes.data, u.ctypes.data, 0), plan)
+    return u
+
+
+def kg_debug_pass(plan, which, spec):
+    spec = np.ascontiguousarray(spec, np.complex128).copy()
+    _check(_lib.kg_debug_pass(plan, which, spec.ctypes.data, 0), plan)
+    return spec
+
+
+def kg_debug_time_kernel(plan, kernel, reps):
+    ms = ctypes.c_float()
+    _check(_lib.kg_debug_time_kernel(plan, kernel, reps, ctypes.byref(ms)), plan)
+    return ms.value
+
+
+def kg_debug_copy(dst_ptr, src_ptr, nbytes, reps, stream=None):
+    ms = ctypes.c_float()
+    _check(_lib.kg_debug_copy(dst_ptr, src_ptr, nbytes, reps, stream, ctypes.byref(ms)))
+    return ms.value
+
+
+def kg_kernel_times(plan):
+    """(average ms per kernel [x, y fwd, z, y inv, finalize], steps averaged)."""
+    ms = (ctypes.c_double * 5)()
+    n = ctypes.c_int()
+    _check(_lib.kg_kernel_times(plan, ms, ctypes.byref(n)), plan)
+    return list(ms), n.value
+
+
+def kg_kernel_bytes(plan, kernel):
+    return _lib.kg_kernel_bytes(plan, kernel)

@@ -1,0 +1,49 @@
+"""The C-ABI library loads on a machine without a GPU and exports every
+function include/kg.h declares; host-only entry points validate arguments."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "kg.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(kg_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("kg_plan", "kg_step", "kg_energy", "kg_set_state", "kg_destroy"):
+        assert required in names
+
+
+def test_library_exports_every_declared_function():
+    from paper_1501_04552_amd import kg
+    lib = ctypes.CDLL(kg.LIB)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(declared_functions()) <= set(kg.EXPORTS)
+
+
+def test_host_side_validation():
+    from paper_1501_04552_amd import kg
+    assert kg.kg_status_str(kg.KG_BLOWUP) == "KG_BLOWUP"
+    assert kg.kg_workspace_bytes(kg.make_params(64, 0.01)) > 0
+    for bad in (kg.make_params(48, 0.01), kg.make_params(1024, 0.01), kg.make_params(100, 0.01),
+                kg.make_params(64, 0.0), kg.make_params(64, -1.0),
+                kg.make_params(64, 0.01, precision=7)):
+        assert kg.kg_workspace_bytes(bad) == 0
+    # sizes of the stored fields: 3 complex fields of n*n*pitch plus small buffers
+    b512 = kg.kg_workspace_bytes(kg.make_params(512, 0.005))
+    assert 3 * 512 * 512 * 257 * 16 < b512 < 3.2 * 512 * 512 * 264 * 16
+    with pytest.raises(kg.KGError) as e:
+        kg.kg_plan(kg.make_params(48, 0.01))
+    assert e.value.status == kg.KG_E_UNSUPPORTED_SIZE
+    with pytest.raises(kg.KGError) as e:
+        kg.kg_plan(kg.make_params(64, 0.0))
+    assert e.value.status == kg.KG_E_INVALID

@@ -272,3 +272,16 @@ def test_eq2_as_dense_linear_solve():
     r = oracle.run(u0, dt, 5, L=Ls, mode=oracle.INIT_TWO_LEVEL, aux=um1)
     assert np.abs(r["u"].ravel() - uc).max() <= 1e-12 * np.abs(uc).max()
     assert np.abs(r["u_prev"].ravel() - up).max() <= 1e-12 * np.abs(up).max()
+
+
+def test_direct_sum_first_step_matches_the_fft_stepper():
+    """The sampled-mode entry (direct DFT sums) and the FFT stepper are two
+    independent routes to v^0 and v^1."""
+    u0 = lumpy(16)
+    modes = [(0, 0, 0), (1, 2, 3), (8, 5, 15), (3, 0, 8), (15, 15, 1)]
+    for lin in (False, True):
+        v0, v1 = oracle.first_step_modes(u0, 0.01, modes, linear_only=lin)
+        vp, vc = oracle.state(u0, 0.01, 1, linear_only=lin)
+        for (ix, iy, iz), a, b in zip(modes, v0, v1):
+            assert abs(a - vp[iz, iy, ix]) <= 1e-13 * np.abs(vp).max()
+            assert abs(b - vc[iz, iy, ix]) <= 1e-13 * np.abs(vc).max()
