@@ -124,6 +124,15 @@ def main():
                for i, name in enumerate(kg.KERNELS)}
     solver.close()
 
+    # achievable-bandwidth ceiling: the library's plain copy kernel, 1 GiB
+    nb = 1 << 30
+    src = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    dst = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    cms = kg.kg_debug_copy(dst.data_ptr(), src.data_ptr(), nb, 20,
+                           torch.cuda.current_stream().cuda_stream)
+    copy_gbs = 2 * nb / (cms * 1e-3) / 1e9
+    del src, dst
+
     steps_per_s = args.steps / elapsed
     sweep = n * n * (n // 2 + 1) * 16
     step_bytes = 11 * sweep
@@ -150,6 +159,7 @@ def main():
         "step_model_GBs": step_bytes / (elapsed / args.steps) / 1e9,
         "step_hbm_frac": step_bytes / (elapsed / args.steps) / 1e9 / HBM_PEAK_GBS,
         "kernels": kernels,
+        "copy_GBs": copy_gbs,
         "energy_drift": drift,
     }
     if not args.no_cpu_baseline and n <= 512:

@@ -7,6 +7,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <new>
@@ -49,7 +50,7 @@ struct kg_plan_s {
     bool own_ws = false;
     size_t ws_bytes = 0;
     char *Q = nullptr, *S[2] = {nullptr, nullptr}, *tw = nullptr;
-    double *partA = nullptr, *partC = nullptr;
+    double *partA = nullptr, *partC = nullptr, *sub = nullptr;
     Rec *rec = nullptr;
     Ctl *ctl = nullptr;
     long nA = 0, nC = 0;
@@ -150,29 +151,42 @@ struct OpsImpl final : Ops {
 };
 
 // Tile width of the y and z passes: W columns of 16-byte complex values give
-// 64-byte row segments per wavefront load.
-constexpr int W64 = 4;
-
-std::unique_ptr<Ops> make_ops(int n, int precision)
+// 16*W-byte row segments per wavefront access.  Whole 128-byte lines (W = 8)
+// stream at 5.5 TB/s where 64-byte segments reach 4.5 (measured at 512^3);
+// KG_TILE_W (4 or 8) overrides the default for experiments.
+int tile_width(int /*n*/)
 {
-    if (precision != KG_FP64) return nullptr;
+    const char *e = std::getenv("KG_TILE_W");
+    if (e && (std::atoi(e) == 4 || std::atoi(e) == 8)) return std::atoi(e);
+    return 8;
+}
+
+template <int W>
+std::unique_ptr<Ops> make_ops_w(int n)
+{
     switch (n) {
-    case 8: return std::make_unique<OpsImpl<double, 8, W64>>();
-    case 16: return std::make_unique<OpsImpl<double, 16, W64>>();
-    case 32: return std::make_unique<OpsImpl<double, 32, W64>>();
-    case 64: return std::make_unique<OpsImpl<double, 64, W64>>();
-    case 128: return std::make_unique<OpsImpl<double, 128, W64>>();
-    case 256: return std::make_unique<OpsImpl<double, 256, W64>>();
-    case 512: return std::make_unique<OpsImpl<double, 512, W64>>();
+    case 8: return std::make_unique<OpsImpl<double, 8, W>>();
+    case 16: return std::make_unique<OpsImpl<double, 16, W>>();
+    case 32: return std::make_unique<OpsImpl<double, 32, W>>();
+    case 64: return std::make_unique<OpsImpl<double, 64, W>>();
+    case 128: return std::make_unique<OpsImpl<double, 128, W>>();
+    case 256: return std::make_unique<OpsImpl<double, 256, W>>();
+    case 512: return std::make_unique<OpsImpl<double, 512, W>>();
     default: return nullptr;
     }
+}
+
+std::unique_ptr<Ops> make_ops(int n, int precision, int W)
+{
+    if (precision != KG_FP64) return nullptr;
+    return W == 8 ? make_ops_w<8>(n) : make_ops_w<4>(n);
 }
 
 bool size_ok(int n) { return n >= 8 && n <= 512 && (n & (n - 1)) == 0; }
 
 struct Layout {
     int n, H, W, ntx, P;
-    size_t esz, q, s, tw, pa, pc, rec, ctl, total;
+    size_t esz, q, s, tw, pa, pc, sub, rec, ctl, total;
     long nA, nC;
 };
 
@@ -181,11 +195,13 @@ bool layout(const kg_params *p, Layout &lo)
     if (!p || !size_ok(p->n) || p->precision != KG_FP64) return false;
     lo.n = p->n;
     lo.H = p->n / 2 + 1;
-    lo.W = W64;
+    lo.W = tile_width(p->n);
     lo.ntx = (lo.H + lo.W - 1) / lo.W;
-    lo.P = lo.ntx * lo.W;
     lo.esz = 16;
-    auto ops = make_ops(p->n, p->precision);
+    // kx rows padded to whole 128-byte lines and to whole tiles
+    const int per_line = (int)(128 / lo.esz);
+    lo.P = ((lo.ntx * lo.W + per_line - 1) / per_line) * per_line;
+    auto ops = make_ops(p->n, p->precision, lo.W);
     lo.nA = ops->x_blocks();
     lo.nC = ops->z_blocks(lo.ntx);
     if (lo.nC < PAIR_BLOCKS) lo.nC = PAIR_BLOCKS;
@@ -195,9 +211,10 @@ bool layout(const kg_params *p, Layout &lo)
     lo.tw = up((size_t)lo.n * lo.esz);
     lo.pa = up((size_t)lo.nA * 2 * sizeof(double));
     lo.pc = up((size_t)lo.nC * 2 * sizeof(double));
+    lo.sub = up((size_t)RSUB * 3 * sizeof(double));
     lo.rec = up((size_t)RING * sizeof(Rec));
     lo.ctl = up(sizeof(Ctl));
-    lo.total = lo.q + 2 * lo.s + lo.tw + lo.pa + lo.pc + lo.rec + lo.ctl;
+    lo.total = lo.q + 2 * lo.s + lo.tw + lo.pa + lo.pc + lo.sub + lo.rec + lo.ctl;
     return true;
 }
 
@@ -315,6 +332,15 @@ kg_status read_ctl(kg_plan_s *pl, Ctl &c)
     return KG_OK;
 }
 
+// Two-launch fixed-order reduction of the partials into a record (see k_finalize).
+void finalize(Plan &p, int nC, double thr, int mode)
+{
+    hipLaunchKernelGGL(k_reduce_partials, dim3(RSUB), dim3(256), 0, p.stream, p.partA, (int)p.nA,
+                       p.partC, nC, p.sub, p.ctl, mode != 2 ? 1 : 0);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RSUB), 0, p.stream, p.sub, p.rec, p.ctl, thr,
+                       p.escale, p.h3, mode);
+}
+
 // Q <- inverse z and y transforms of level S (scaled by 1/M): what the x pass
 // of the next step expects.
 kg_status prepare_q(kg_plan_s *pl, const void *S)
@@ -400,7 +426,7 @@ kg_status kg_plan(const kg_params *p, void *d_workspace, size_t ws_bytes, void *
     pl->nC = lo.nC;
     pl->q_bytes = lo.q;
     pl->s_bytes = lo.s;
-    pl->ops = make_ops(p->n, p->precision);
+    pl->ops = make_ops(p->n, p->precision, lo.W);
 
     if (d_workspace) {
         pl->ws = d_workspace;
@@ -427,6 +453,8 @@ kg_status kg_plan(const kg_params *p, void *d_workspace, size_t ws_bytes, void *
     c += lo.pa;
     pl->partC = (double *)c;
     c += lo.pc;
+    pl->sub = (double *)c;
+    c += lo.sub;
     pl->rec = (Rec *)c;
     c += lo.rec;
     pl->ctl = (Ctl *)c;
@@ -500,8 +528,7 @@ kg_status kg_set_state(kg_plan_t *plan, const double *u0, const double *aux, int
     p.ops->pair_energy(p, S1, S0);
     if ((s = prepare_q(plan, S1)) != KG_OK) return s;
     p.ops->x(p, X_REDUCE, nullptr, nullptr, 0.0);
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, p.stream, p.partA, (int)p.nA, p.partC,
-                       PAIR_BLOCKS, p.rec, p.ctl, 0.0, p.escale, p.h3, 2);
+    finalize(p, PAIR_BLOCKS, 0.0, 2);
     LAUNCHCHK(plan);
     if ((s = prepare_q(plan, S0)) != KG_OK) return s;
     HIPCHK(plan, hipStreamSynchronize(p.stream));
@@ -538,9 +565,7 @@ kg_status kg_step(kg_plan_t *plan, int nsteps, unsigned flags, int *steps_done)
         if (timed) HIPCHK(plan, hipEventRecord(ev[3], p.stream));
         p.ops->y(p, 1, true);
         if (timed) HIPCHK(plan, hipEventRecord(ev[4], p.stream));
-        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, p.stream, p.partA, (int)p.nA,
-                           p.partC, (int)p.ops->z_blocks(p.ntx), p.rec, p.ctl, thr, p.escale,
-                           p.h3, 0);
+        finalize(p, (int)p.ops->z_blocks(p.ntx), thr, 0);
         if (timed) HIPCHK(plan, hipEventRecord(ev[5], p.stream));
     }
     LAUNCHCHK(plan);
@@ -584,8 +609,7 @@ kg_status kg_energy(kg_plan_t *plan, double *E, double *t)
     if (!p.ready) return fail(plan, KG_E_INVALID, "kg_set_state has not been called");
     // Q4 of the newest level from its working field (reductions only).
     p.ops->x(p, X_REDUCE, nullptr, nullptr, 0.0);
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, p.stream, p.partA, (int)p.nA, p.partC,
-                       0, p.rec, p.ctl, 0.0, p.escale, p.h3, 1);
+    finalize(p, 0, 0.0, 1);
     LAUNCHCHK(plan);
     Ctl c;
     kg_status s = read_ctl(plan, c);

@@ -52,6 +52,25 @@ __device__ __forceinline__ cx<T> conjg(cx<T> a) { return mk(a.re, -a.im); }
 template <typename T>
 __device__ __forceinline__ cx<T> scale(cx<T> a, T s) { return mk(a.re * s, a.im * s); }
 
+// Streaming global accesses (each value is read or written once per pass):
+// nontemporal hints keep them from displacing reused data in the caches.
+template <typename T>
+__device__ __forceinline__ cx<T> ld_nt(const cx<T> *p)
+{
+    typedef T v2 __attribute__((ext_vector_type(2)));
+    const v2 v = __builtin_nontemporal_load(reinterpret_cast<const v2 *>(p));
+    return mk(v.x, v.y);
+}
+template <typename T>
+__device__ __forceinline__ void st_nt(cx<T> *p, cx<T> a)
+{
+    typedef T v2 __attribute__((ext_vector_type(2)));
+    v2 v;
+    v.x = a.re;
+    v.y = a.im;
+    __builtin_nontemporal_store(v, reinterpret_cast<v2 *>(p));
+}
+
 // Multiply by -i (DIR = -1, forward) or +i (DIR = +1, inverse).
 template <int DIR, typename T>
 __device__ __forceinline__ cx<T> rot90(cx<T> a)
@@ -127,12 +146,53 @@ struct Radix {
     static_assert((1 << LG) == NL, "line length must be a power of two");
 };
 
+// LDS slot of line position p: one padding slot after every 8 positions, so
+// the strided writes of the early stages spread over the LDS banks.
+__device__ __forceinline__ int lpos(int p) { return p + (p >> 3); }
+template <int NL>
+constexpr int lslots() { return NL + NL / 8; }
+
+// Synchronisation between the stages of one line: the whole workgroup
+// (lines spread over several waves) or one wave (every thread of the line,
+// and of every line sharing its LDS, sits in the same wavefront; LDS
+// operations of a wave complete in issue order, so a compiler fence is enough).
+enum { SYNC_BLOCK = 0, SYNC_WAVE = 1 };
+template <int SY>
+__device__ __forceinline__ void stage_sync()
+{
+    if constexpr (SY == SYNC_BLOCK) {
+        __syncthreads();
+    } else {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
+// Twiddles w^r, r = 1..R-1, of one butterfly from the table entries w, w^2
+// and w^4 (each at most two products away from a table value).
+template <int R, typename T>
+__device__ __forceinline__ void twiddles(cx<T> (&w)[R], const cx<T> *__restrict__ tw, int idx)
+{
+    w[1] = tw[idx];
+    if constexpr (R >= 4) {
+        w[2] = tw[2 * idx];
+        w[3] = cmul(w[1], w[2]);
+    }
+    if constexpr (R == 8) {
+        w[4] = tw[4 * idx];
+        w[5] = cmul(w[1], w[4]);
+        w[6] = cmul(w[2], w[4]);
+        w[7] = cmul(w[3], w[4]);
+    }
+}
+
 // Stockham stages S..NST-1 of a line.  v holds the owned positions on entry
-// to stage 0 and on exit from the last stage.  lds points at position 0 of
-// this line in an LDS buffer in which consecutive positions are `ls`
-// elements apart.  tw is the table exp(-2 pi i j / NTAB) with NTAB = NL * twm.
-// Callers must make sure nobody still reads the LDS line when calling.
-template <typename T, int NL, int DIR, int S = 0>
+// to stage 0 and on exit from the last stage.  lds points at slot 0 of this
+// line in an LDS buffer where consecutive slots are `ls` elements apart (the
+// line needs lslots<NL>() slots).  tw is the table exp(-2 pi i j / NTAB) with
+// NTAB = NL * twm.  Callers must make sure nobody still reads the LDS line.
+template <typename T, int NL, int DIR, int SY = SYNC_BLOCK, int S = 0>
 __device__ __forceinline__ void fft_line(cx<T> (&v)[Radix<NL>::E], cx<T> *lds, int ls, int t,
                                          const cx<T> *__restrict__ tw, int twm)
 {
@@ -141,10 +201,10 @@ __device__ __forceinline__ void fft_line(cx<T> (&v)[Radix<NL>::E], cx<T> *lds, i
     constexpr int R = P::radix(S), L = P::lbefore(S);
     constexpr bool last = (S == P::NST - 1);
     if constexpr (S > 0) {
-        __syncthreads();
+        stage_sync<SY>();
 #pragma unroll
-        for (int j = 0; j < E; ++j) v[j] = lds[(t + j * TPL) * ls];
-        if constexpr (!last) __syncthreads();
+        for (int j = 0; j < E; ++j) v[j] = lds[lpos(t + j * TPL) * ls];
+        if constexpr (!last) stage_sync<SY>();
     }
 #pragma unroll
     for (int b = 0; b < E / R; ++b) {
@@ -154,11 +214,10 @@ __device__ __forceinline__ void fft_line(cx<T> (&v)[Radix<NL>::E], cx<T> *lds, i
 #pragma unroll
         for (int r = 0; r < R; ++r) x[r] = v[b + r * (E / R)];
         if constexpr (L > 1) {
+            cx<T> w[R];
+            twiddles<R>(w, tw, k * (NL / (L * R)) * twm);
 #pragma unroll
-            for (int r = 1; r < R; ++r) {
-                const cx<T> w = tw[r * k * (NL / (L * R)) * twm];
-                x[r] = (DIR < 0) ? cmul(x[r], w) : cmulc(x[r], w);
-            }
+            for (int r = 1; r < R; ++r) x[r] = (DIR < 0) ? cmul(x[r], w[r]) : cmulc(x[r], w[r]);
         }
         dft<R, DIR>(x);
         if constexpr (last) {
@@ -167,10 +226,10 @@ __device__ __forceinline__ void fft_line(cx<T> (&v)[Radix<NL>::E], cx<T> *lds, i
         } else {
             const int base = (i / L) * L * R + k;
 #pragma unroll
-            for (int s = 0; s < R; ++s) lds[(base + s * L) * ls] = x[s];
+            for (int s = 0; s < R; ++s) lds[lpos(base + s * L) * ls] = x[s];
         }
     }
-    if constexpr (!last) fft_line<T, NL, DIR, S + 1>(v, lds, ls, t, tw, twm);
+    if constexpr (!last) fft_line<T, NL, DIR, SY, S + 1>(v, lds, ls, t, tw, twm);
 }
 
 }  // namespace kg

@@ -112,7 +112,7 @@ struct XCfg {
     static constexpr int TPL = Radix<NH>::TPL;
     static constexpr int NT = 256;
     static constexpr int LPB = NT / TPL;  // lines per workgroup
-    static constexpr int RS = NH + 1;     // LDS row stride
+    static constexpr int RS = lslots<NH>() + 1;  // LDS row stride (slots)
     static constexpr long blocks() { return ((long)N * N + LPB - 1) / LPB; }
 };
 
@@ -121,6 +121,8 @@ __global__ __launch_bounds__(256) void k_xpass(XArgs<T> a)
 {
     using C = XCfg<N>;
     constexpr int NH = C::NH, E = Radix<NH>::E, TPL = C::TPL, LPB = C::LPB, RS = C::RS;
+    // a line's threads never span two waves, so its stages sync per wave
+    constexpr int XSY = (64 % TPL == 0) ? SYNC_WAVE : SYNC_BLOCK;
     __shared__ cx<T> rows[LPB * RS];
     if constexpr (MODE == X_STEP || MODE == X_REDUCE) {
         if (a.ctl->flag) return;
@@ -148,15 +150,15 @@ __global__ __launch_bounds__(256) void k_xpass(XArgs<T> a)
         }
     } else {
         cx<T> *q = a.Q + line * a.P;
-        for (int e = t; e < NH + 1; e += TPL) r[e] = act ? q[e] : zero;
-        __syncthreads();
+        for (int e = t; e < NH + 1; e += TPL) r[lpos(e)] = act ? ld_nt(q + e) : zero;
+        stage_sync<XSY>();
         // Hermitian half line X[0..NH] -> Z[k] = E[k] + i O[k] with
         // E[k] = X[k] + conj(X[NH-k]), O[k] = (X[k] - conj(X[NH-k])) e^{+2 pi i k/N};
         // the imaginary parts of X[0] and X[NH] are dropped (real field).
 #pragma unroll
         for (int j = 0; j < E; ++j) {
             const int k = t + j * TPL;
-            cx<T> xk = r[k], xm = r[NH - k];
+            cx<T> xk = r[lpos(k)], xm = r[lpos(NH - k)];
             if (k == 0) {
                 xk.im = 0;
                 xm.im = 0;
@@ -164,8 +166,8 @@ __global__ __launch_bounds__(256) void k_xpass(XArgs<T> a)
             const cx<T> sum = xk + conjg(xm), dif = xk - conjg(xm);
             v[j] = sum + rot90<1>(cmulc(dif, a.tw[k]));
         }
-        __syncthreads();
-        fft_line<T, NH, 1>(v, r, 1, t, a.tw, 2);
+        stage_sync<XSY>();
+        fft_line<T, NH, 1, XSY>(v, r, 1, t, a.tw, 2);
         // v[j] = u[2m] + i u[2m+1], m = t + j*TPL
         if constexpr (MODE == X_C2R) {
             if (act) {
@@ -196,25 +198,25 @@ __global__ __launch_bounds__(256) void k_xpass(XArgs<T> a)
             const T u0 = v[j].re, u1 = v[j].im;
             v[j] = mk(a.chi * u0 * u0 * u0, a.chi * u1 * u1 * u1);
         }
-        __syncthreads();
+        stage_sync<XSY>();
     }
-    fft_line<T, NH, -1>(v, r, 1, t, a.tw, 2);
+    fft_line<T, NH, -1, XSY>(v, r, 1, t, a.tw, 2);
     // Z'[k] -> W[k] = Ev[k] + e^{-2 pi i k/N} Od[k], k = 0..NH, with
     // Ev = (Z'[k] + conj Z'[NH-k])/2, Od = (Z'[k] - conj Z'[NH-k])/(2i).
-    __syncthreads();
+    stage_sync<XSY>();
 #pragma unroll
-    for (int j = 0; j < E; ++j) r[t + j * TPL] = v[j];
-    __syncthreads();
+    for (int j = 0; j < E; ++j) r[lpos(t + j * TPL)] = v[j];
+    stage_sync<XSY>();
     if (act) {
         cx<T> *q = a.Q + line * a.P;
 #pragma unroll
         for (int j = 0; j < E; ++j) {
             const int k = t + j * TPL;
-            const cx<T> zk = r[k], zm = conjg(r[(NH - k) & (NH - 1)]);
+            const cx<T> zk = r[lpos(k)], zm = conjg(r[lpos((NH - k) & (NH - 1))]);
             const cx<T> ev = scale(zk + zm, (T)0.5);
             const cx<T> od = scale(rot90<-1>(zk - zm), (T)0.5);
-            q[k] = ev + cmul(od, a.tw[k]);
-            if (k == 0) q[NH] = ev - od;
+            st_nt(q + k, ev + cmul(od, a.tw[k]));
+            if (k == 0) st_nt(q + NH, ev - od);
         }
     }
     if constexpr (MODE == X_STEP) block_max_sum<256>(mx, s4, a.part + 2 * blockIdx.x);
@@ -245,7 +247,7 @@ __global__ __launch_bounds__((YZCfg<N, W>::NT)) void k_ypass(YArgs<T> a)
 {
     using C = YZCfg<N, W>;
     constexpr int E = Radix<N>::E, TPL = C::TPL, B = C::B;
-    __shared__ cx<T> lds[W * B * N];
+    __shared__ cx<T> lds[W * B * lslots<N>()];
     if (a.ctl && a.ctl->flag) return;
     const int c = threadIdx.x % W, t = (threadIdx.x / W) % TPL, b = threadIdx.x / (W * TPL);
     const int tile = blockIdx.x % a.ntx, z = (blockIdx.x / a.ntx) * B + b;
@@ -254,11 +256,11 @@ __global__ __launch_bounds__((YZCfg<N, W>::NT)) void k_ypass(YArgs<T> a)
     cx<T> *g = a.Q + ((long)z * N) * a.P + kx;
     cx<T> v[E];
 #pragma unroll
-    for (int j = 0; j < E; ++j) v[j] = act ? g[(long)(t + j * TPL) * a.P] : mk<T>(0, 0);
+    for (int j = 0; j < E; ++j) v[j] = act ? ld_nt(g + (long)(t + j * TPL) * a.P) : mk<T>(0, 0);
     fft_line<T, N, DIR>(v, lds + c + W * b, W * B, t, a.tw, 1);
     if (act) {
 #pragma unroll
-        for (int j = 0; j < E; ++j) g[(long)(t + j * TPL) * a.P] = v[j];
+        for (int j = 0; j < E; ++j) st_nt(g + (long)(t + j * TPL) * a.P, v[j]);
     }
 }
 
@@ -307,7 +309,7 @@ __global__ __launch_bounds__((YZCfg<N, W>::NT)) void k_zpass(ZArgs<T> a)
 {
     using C = YZCfg<N, W>;
     constexpr int E = Radix<N>::E, TPL = C::TPL, B = C::B, NT = C::NT;
-    __shared__ cx<T> lds[W * B * N];
+    __shared__ cx<T> lds[W * B * lslots<N>()];
     if constexpr (MODE == Z_STEP) {
         if (a.ctl->flag) return;
     }
@@ -325,7 +327,7 @@ __global__ __launch_bounds__((YZCfg<N, W>::NT)) void k_zpass(ZArgs<T> a)
     if constexpr (MODE == Z_STEP || MODE == Z_FWD_STATE || MODE == Z_FWD_Q || MODE == Z_START) {
         if (MODE != Z_START || a.has_vel) {
 #pragma unroll
-            for (int j = 0; j < E; ++j) v[j] = act ? g[(t + j * TPL) * zs] : zero;
+            for (int j = 0; j < E; ++j) v[j] = act ? ld_nt(g + (t + j * TPL) * zs) : zero;
             fft_line<T, N, -1>(v, lline, W * B, t, a.tw, 1);
         } else {
 #pragma unroll
@@ -378,11 +380,11 @@ __global__ __launch_bounds__((YZCfg<N, W>::NT)) void k_zpass(ZArgs<T> a)
                 double al, be, w2;
                 coeffs(kx, my, mz, a.ks2, a.dt, al, be, w2);
                 const long si = sbase + (long)kz * W;
-                const cx<T> vc = a.Sc[si], vp = a.Sp[si];
+                const cx<T> vc = ld_nt(a.Sc + si), vp = ld_nt(a.Sp + si);
                 const double re = al * (double)vc.re - (double)vp.re + be * (double)v[j].re;
                 const double im = al * (double)vc.im - (double)vp.im + be * (double)v[j].im;
                 nv = mk((T)re, (T)im);
-                a.Sp[si] = nv;
+                st_nt(a.Sp + si, nv);
                 const double dr = (double)nv.re - (double)vc.re, di = (double)nv.im - (double)vc.im;
                 const double sr = (double)nv.re + (double)vc.re, sim = (double)nv.im + (double)vc.im;
                 esum += wgt * ((dr * dr + di * di) * idt2 + 0.25 * w2 * (sr * sr + sim * sim));
@@ -402,7 +404,7 @@ __global__ __launch_bounds__((YZCfg<N, W>::NT)) void k_zpass(ZArgs<T> a)
     fft_line<T, N, 1>(v, lline, W * B, t, a.tw, 1);
     if (act) {
 #pragma unroll
-        for (int j = 0; j < E; ++j) g[(t + j * TPL) * zs] = v[j];
+        for (int j = 0; j < E; ++j) st_nt(g + (t + j * TPL) * zs, v[j]);
     }
     if constexpr (MODE == Z_STEP) block_max_sum<NT>(0.0, esum, a.part + 2 * blockIdx.x);
 }
@@ -451,28 +453,60 @@ __global__ __launch_bounds__(256) void k_state_to_spec(const cx<T> *S, double *o
     }
 }
 
-// Fixed-order reduction of the workgroup partials of a step.
-//   mode 0 (step):   rec[step] = {elin, q4, maxu}; blow-up test; step counter.
-//   mode 1 (reduce): rec[step].q4/maxu from the x-pass partials only.
-//   mode 2 (init):   ctl->elin_m, q4_m, maxu_m.
-__global__ __launch_bounds__(256) void k_finalize(const double *partA, int nA, const double *partC,
-                                                  int nC, Rec *rec, Ctl *ctl, double thr,
-                                                  double escale, double h3, int mode)
+// Fixed-order reduction of the workgroup partials, in two launches so that
+// many workgroups share the reading: k_reduce_partials folds contiguous slices
+// of the x-pass partials (max, sum) and z-pass partials (sum) into RSUB
+// sub-partials, then k_finalize folds those.  Both use fixed index orders, so
+// the result is bitwise reproducible.
+constexpr int RSUB = 128;
+
+__global__ __launch_bounds__(256) void k_reduce_partials(const double *partA, int nA,
+                                                         const double *partC, int nC, double *sub,
+                                                         const Ctl *ctl, int check_flag)
 {
-    if (mode != 2 && ctl->flag) return;
+    if (check_flag && ctl->flag) return;
+    const int b = blockIdx.x;
+    const int a0 = (int)((long)nA * b / RSUB), a1 = (int)((long)nA * (b + 1) / RSUB);
+    const int c0 = (int)((long)nC * b / RSUB), c1 = (int)((long)nC * (b + 1) / RSUB);
     double mx = 0.0, s4 = 0.0, se = 0.0;
-    for (int i = threadIdx.x; i < nA; i += 256) {
+    for (int i = a0 + (int)threadIdx.x; i < a1; i += 256) {
         mx = nanmax(mx, partA[2 * i]);
         s4 += partA[2 * i + 1];
     }
-    if (mode != 1)
-        for (int i = threadIdx.x; i < nC; i += 256) se += partC[2 * i + 1];
+    for (int i = c0 + (int)threadIdx.x; i < c1; i += 256) se += partC[2 * i + 1];
     __shared__ double red[3][256];
     red[0][threadIdx.x] = mx;
     red[1][threadIdx.x] = s4;
     red[2][threadIdx.x] = se;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            red[0][threadIdx.x] = nanmax(red[0][threadIdx.x], red[0][threadIdx.x + s]);
+            red[1][threadIdx.x] += red[1][threadIdx.x + s];
+            red[2][threadIdx.x] += red[2][threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        sub[3 * b] = red[0][0];
+        sub[3 * b + 1] = red[1][0];
+        sub[3 * b + 2] = red[2][0];
+    }
+}
+
+//   mode 0 (step):   rec[step] = {elin, q4, maxu}; blow-up test; step counter.
+//   mode 1 (reduce): rec[step].q4/maxu from the x-pass partials only.
+//   mode 2 (init):   ctl->elin_m, q4_m, maxu_m.
+__global__ __launch_bounds__(RSUB) void k_finalize(const double *sub, Rec *rec, Ctl *ctl,
+                                                   double thr, double escale, double h3, int mode)
+{
+    if (mode != 2 && ctl->flag) return;
+    __shared__ double red[3][RSUB];
+    red[0][threadIdx.x] = sub[3 * threadIdx.x];
+    red[1][threadIdx.x] = sub[3 * threadIdx.x + 1];
+    red[2][threadIdx.x] = mode == 1 ? 0.0 : sub[3 * threadIdx.x + 2];
+    __syncthreads();
+    for (int s = RSUB / 2; s > 0; s >>= 1) {
         if ((int)threadIdx.x < s) {
             red[0][threadIdx.x] = nanmax(red[0][threadIdx.x], red[0][threadIdx.x + s]);
             red[1][threadIdx.x] += red[1][threadIdx.x + s];

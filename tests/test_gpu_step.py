@@ -186,7 +186,9 @@ def test_first_step_at_512_sampled_modes(kg):
 
 
 def test_uniform_recurrence_at_512(kg):
-    """Uniform data at full size follows the oracle's uniform run exactly."""
+    """Uniform data at full size follows the oracle's uniform run.  Both sides
+    round every step; the difference grows like steps * log2(M) * eps
+    (50 * 27 * 1.1e-16 ~ 1.5e-13 relative), so 1e-12 relative is the bound."""
     n, dt, steps = 512, 0.005, 50
     ref = oracle.run(ki.uniform(8, 0.5), dt, steps)
     with kg.Solver(n, dt) as s:
@@ -194,4 +196,4 @@ def test_uniform_recurrence_at_512(kg):
         s.step(steps)
         u = s.u()
     assert np.ptp(u) <= 1e-12
-    assert abs(u[0, 0, 0] - ref["u"][0, 0, 0]) <= 1e-13
+    assert abs(u[0, 0, 0] - ref["u"][0, 0, 0]) <= 1e-12 * abs(ref["u"][0, 0, 0])
