@@ -106,87 +106,89 @@ struct XArgs {
     T chi;                // cubic coefficient (X_STEP; X_R2C: 1 cubes the input)
 };
 
+// Two real x-lines u1, u2 are transformed together as one complex line
+// z = u1 + i u2 of N points: their half spectra X1, X2 (kx = 0..N/2) give
+//   Z[k] = X1[k] + i X2[k],  with X[k] = conj(X[N-k]) for k > N/2
+// (imaginary parts of X[0] and X[N/2] dropped: the fields are real), and
+// the forward transform Z' of (u1^3 + i u2^3) splits back into
+//   W1[k] = (Z'[k] + conj Z'[N-k]) / 2,  W2[k] = (Z'[k] - conj Z'[N-k]) / (2i).
 template <int N>
 struct XCfg {
-    static constexpr int NH = N / 2;
-    static constexpr int TPL = Radix<NH>::TPL;
+    static constexpr int TPL = Radix<N>::TPL;
     static constexpr int NT = 256;
-    static constexpr int LPB = NT / TPL;  // lines per workgroup
-    static constexpr int RS = lslots<NH>() + 1;  // LDS row stride (slots)
-    static constexpr long blocks() { return ((long)N * N + LPB - 1) / LPB; }
+    static constexpr int PPB = NT / TPL;  // line pairs per workgroup
+    static constexpr int RS = lslots<N>();
+    static constexpr long blocks() { return ((long)N * N / 2 + PPB - 1) / PPB; }
 };
 
 template <typename T, int N, int MODE>
 __global__ __launch_bounds__(256) void k_xpass(XArgs<T> a)
 {
     using C = XCfg<N>;
-    constexpr int NH = C::NH, E = Radix<NH>::E, TPL = C::TPL, LPB = C::LPB, RS = C::RS;
-    // a line's threads never span two waves, so its stages sync per wave
+    constexpr int E = Radix<N>::E, TPL = C::TPL, PPB = C::PPB, RS = C::RS, NH = N / 2;
+    // a pair's threads never span two waves, so its stages sync per wave
     constexpr int XSY = (64 % TPL == 0) ? SYNC_WAVE : SYNC_BLOCK;
-    __shared__ cx<T> rows[LPB * RS];
+    __shared__ cx<T> rows[PPB * RS];
     if constexpr (MODE == X_STEP || MODE == X_REDUCE) {
         if (a.ctl->flag) return;
     }
     const int t = threadIdx.x % TPL, l = threadIdx.x / TPL;
-    const long line = (long)blockIdx.x * LPB + l;
-    const bool act = line < (long)N * N;
+    const long pr = (long)blockIdx.x * PPB + l;
+    const bool act = pr < (long)N * N / 2;
     cx<T> *r = rows + l * RS;
-    const cx<T> zero = mk<T>(0, 0);
     cx<T> v[E];
     double mx = 0.0, s4 = 0.0;
 
     if constexpr (MODE == X_R2C) {
-        // packed real line: z[m] = x[2m] + i x[2m+1]
-        const double *src = a.rin + line * N;
+        const double *s1 = a.rin + (2 * pr) * N, *s2 = s1 + N;
 #pragma unroll
         for (int j = 0; j < E; ++j) {
             const int m = t + j * TPL;
-            T x0 = act ? (T)src[2 * m] : (T)0, x1 = act ? (T)src[2 * m + 1] : (T)0;
+            T x1 = act ? (T)s1[m] : (T)0, x2 = act ? (T)s2[m] : (T)0;
             if (a.chi != (T)0) {
-                x0 = x0 * x0 * x0;
                 x1 = x1 * x1 * x1;
+                x2 = x2 * x2 * x2;
             }
-            v[j] = mk(x0, x1);
+            v[j] = mk(x1, x2);
         }
     } else {
-        cx<T> *q = a.Q + line * a.P;
-        for (int e = t; e < NH + 1; e += TPL) r[lpos(e)] = act ? ld_nt(q + e) : zero;
-        stage_sync<XSY>();
-        // Hermitian half line X[0..NH] -> Z[k] = E[k] + i O[k] with
-        // E[k] = X[k] + conj(X[NH-k]), O[k] = (X[k] - conj(X[NH-k])) e^{+2 pi i k/N};
-        // the imaginary parts of X[0] and X[NH] are dropped (real field).
+        const cx<T> *q1 = a.Q + (2 * pr) * a.P, *q2 = q1 + a.P;
 #pragma unroll
         for (int j = 0; j < E; ++j) {
             const int k = t + j * TPL;
-            cx<T> xk = r[lpos(k)], xm = r[lpos(NH - k)];
-            if (k == 0) {
-                xk.im = 0;
-                xm.im = 0;
+            const int m = k <= NH ? k : N - k;
+            cx<T> x1 = mk<T>(0, 0), x2 = mk<T>(0, 0);
+            if (act) {
+                x1 = ld_nt(q1 + m);
+                x2 = ld_nt(q2 + m);
             }
-            const cx<T> sum = xk + conjg(xm), dif = xk - conjg(xm);
-            v[j] = sum + rot90<1>(cmulc(dif, a.tw[k]));
+            if (k == 0 || k == NH) {
+                x1.im = 0;
+                x2.im = 0;
+            }
+            // Z = X1 + i X2 (k <= N/2), conj(X1) + i conj(X2) (k > N/2)
+            v[j] = k <= NH ? mk(x1.re - x2.im, x1.im + x2.re) : mk(x1.re + x2.im, x2.re - x1.im);
         }
-        stage_sync<XSY>();
-        fft_line<T, NH, 1, XSY>(v, r, 1, t, a.tw, 2);
-        // v[j] = u[2m] + i u[2m+1], m = t + j*TPL
+        fft_line<T, N, 1, XSY>(v, r, 1, t, a.tw, 1);
+        // v[j] = u1[m] + i u2[m], m = t + j*TPL
         if constexpr (MODE == X_C2R) {
             if (act) {
-                double *dst = a.rout + line * N;
+                double *d1 = a.rout + (2 * pr) * N, *d2 = d1 + N;
 #pragma unroll
                 for (int j = 0; j < E; ++j) {
                     const int m = t + j * TPL;
-                    dst[2 * m] = (double)v[j].re;
-                    dst[2 * m + 1] = (double)v[j].im;
+                    d1[m] = (double)v[j].re;
+                    d2[m] = (double)v[j].im;
                 }
             }
             return;
         }
 #pragma unroll
         for (int j = 0; j < E; ++j) {
-            const double u0 = (double)v[j].re, u1 = (double)v[j].im;
+            const double u1 = (double)v[j].re, u2 = (double)v[j].im;
             if (act) {
-                mx = nanmax(mx, nanmax(fabs(u0), fabs(u1)));
-                s4 += u0 * u0 * u0 * u0 + u1 * u1 * u1 * u1;
+                mx = nanmax(mx, nanmax(fabs(u1), fabs(u2)));
+                s4 += u1 * u1 * u1 * u1 + u2 * u2 * u2 * u2;
             }
         }
         if constexpr (MODE == X_REDUCE) {
@@ -195,28 +197,31 @@ __global__ __launch_bounds__(256) void k_xpass(XArgs<T> a)
         }
 #pragma unroll
         for (int j = 0; j < E; ++j) {
-            const T u0 = v[j].re, u1 = v[j].im;
-            v[j] = mk(a.chi * u0 * u0 * u0, a.chi * u1 * u1 * u1);
+            const T u1 = v[j].re, u2 = v[j].im;
+            v[j] = mk(a.chi * u1 * u1 * u1, a.chi * u2 * u2 * u2);
         }
         stage_sync<XSY>();
     }
-    fft_line<T, NH, -1, XSY>(v, r, 1, t, a.tw, 2);
-    // Z'[k] -> W[k] = Ev[k] + e^{-2 pi i k/N} Od[k], k = 0..NH, with
-    // Ev = (Z'[k] + conj Z'[NH-k])/2, Od = (Z'[k] - conj Z'[NH-k])/(2i).
+    fft_line<T, N, -1, XSY>(v, r, 1, t, a.tw, 1);
+    // positions >= N/2 are the partners N-k of the outputs k = 1..N/2
     stage_sync<XSY>();
 #pragma unroll
-    for (int j = 0; j < E; ++j) r[lpos(t + j * TPL)] = v[j];
+    for (int j = 0; j < E; ++j) {
+        const int k = t + j * TPL;
+        if (k >= NH) r[lpos(k)] = v[j];
+    }
     stage_sync<XSY>();
     if (act) {
-        cx<T> *q = a.Q + line * a.P;
+        cx<T> *q1 = a.Q + (2 * pr) * a.P, *q2 = q1 + a.P;
 #pragma unroll
         for (int j = 0; j < E; ++j) {
             const int k = t + j * TPL;
-            const cx<T> zk = r[lpos(k)], zm = conjg(r[lpos((NH - k) & (NH - 1))]);
-            const cx<T> ev = scale(zk + zm, (T)0.5);
-            const cx<T> od = scale(rot90<-1>(zk - zm), (T)0.5);
-            st_nt(q + k, ev + cmul(od, a.tw[k]));
-            if (k == 0) st_nt(q + NH, ev - od);
+            if (k <= NH) {
+                const cx<T> zk = v[j];
+                const cx<T> zm = k == 0 ? conjg(zk) : conjg(r[lpos(N - k)]);
+                st_nt(q1 + k, scale(zk + zm, (T)0.5));
+                st_nt(q2 + k, scale(rot90<-1>(zk - zm), (T)0.5));
+            }
         }
     }
     if constexpr (MODE == X_STEP) block_max_sum<256>(mx, s4, a.part + 2 * blockIdx.x);
