@@ -59,6 +59,8 @@ struct kg_plan_s {
     bool ready = false;
     std::unique_ptr<Ops> ops;
     std::vector<hipEvent_t> tev;  // events of KG_STEP_TIMED calls
+    hipStream_t cap = nullptr;    // private stream used only to capture graphs
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};  // GRAPH_STEPS steps from parity 0 / 1
     double kt_ms[5] = {0, 0, 0, 0, 0};
     int kt_steps = 0;
     std::string err;
@@ -485,6 +487,9 @@ void kg_destroy(kg_plan_t *plan)
 {
     if (!plan) return;
     for (hipEvent_t e : plan->tev) (void)hipEventDestroy(e);
+    for (hipGraphExec_t g : plan->gexec)
+        if (g) (void)hipGraphExecDestroy(g);
+    if (plan->cap) (void)hipStreamDestroy(plan->cap);
     if (plan->own_ws && plan->ws) (void)hipFree(plan->ws);
     delete plan;
 }
@@ -537,6 +542,52 @@ kg_status kg_set_state(kg_plan_t *plan, const double *u0, const double *aux, int
     return KG_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Enqueue the kernels of step m (levels v^{m-1}, v^m -> v^{m+1}) on stream st.
+void enqueue_step(Plan &p, long m, hipStream_t st)
+{
+    void *Sc = p.S[m & 1], *Sp = p.S[(m + 1) & 1];
+    hipStream_t keep = p.stream;
+    p.stream = st;
+    p.ops->x(p, X_STEP, nullptr, nullptr, p.chi);
+    p.ops->y(p, -1, true);
+    p.ops->z(p, Z_STEP, Sp, Sc, p.invM, 0);
+    p.ops->y(p, 1, true);
+    finalize(p, (int)p.ops->z_blocks(p.ntx), p.p.blowup_threshold, 0);
+    p.stream = keep;
+}
+
+constexpr int GRAPH_STEPS = 8;  // steps per captured graph (even: parity returns)
+
+// The graph of GRAPH_STEPS steps starting at a level of parity `par`,
+// captured once on the plan's private stream and replayed on its stream.
+kg_status step_graph(Plan &p, int par, hipGraphExec_t &out)
+{
+    if (!p.gexec[par]) {
+        if (!p.cap) HIPCHK(&p, hipStreamCreateWithFlags(&p.cap, hipStreamNonBlocking));
+        hipGraph_t g = nullptr;
+        HIPCHK(&p, hipStreamBeginCapture(p.cap, hipStreamCaptureModeThreadLocal));
+        for (int i = 0; i < GRAPH_STEPS; ++i) enqueue_step(p, par + i, p.cap);
+        hipError_t e = hipStreamEndCapture(p.cap, &g);
+        if (e != hipSuccess) return hip_fail(&p, e, "hipStreamEndCapture");
+        e = hipGraphInstantiate(&p.gexec[par], g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            p.gexec[par] = nullptr;
+            return hip_fail(&p, e, "hipGraphInstantiate");
+        }
+    }
+    out = p.gexec[par];
+    return KG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 kg_status kg_step(kg_plan_t *plan, int nsteps, unsigned flags, int *steps_done)
 {
     if (!plan || nsteps < 0) return KG_E_INVALID;
@@ -544,6 +595,28 @@ kg_status kg_step(kg_plan_t *plan, int nsteps, unsigned flags, int *steps_done)
     if (!p.ready) return fail(plan, KG_E_INVALID, "kg_set_state has not been called");
     const double thr = p.p.blowup_threshold;
     const bool timed = (flags & KG_STEP_TIMED) != 0;
+    if (!timed && nsteps >= GRAPH_STEPS) {
+        // whole graphs of GRAPH_STEPS steps, then single steps
+        int done = 0;
+        while (nsteps - done >= GRAPH_STEPS) {
+            hipGraphExec_t ge;
+            kg_status s = step_graph(p, (int)((p.steps + done) & 1), ge);
+            if (s != KG_OK) return s;
+            HIPCHK(plan, hipGraphLaunch(ge, p.stream));
+            done += GRAPH_STEPS;
+        }
+        for (; done < nsteps; ++done) enqueue_step(p, p.steps + done, p.stream);
+        LAUNCHCHK(plan);
+        p.steps += nsteps;
+        if (flags & KG_STEP_SYNC) {
+            Ctl c;
+            kg_status s = read_ctl(plan, c);
+            if (s != KG_OK) return s;
+            if (steps_done) *steps_done = c.step;
+            if (c.flag) return KG_BLOWUP;
+        }
+        return KG_OK;
+    }
     if (timed) {
         const size_t need = (size_t)6 * nsteps;
         while (p.tev.size() < need) {
@@ -891,7 +964,7 @@ kg_status kg_debug_copy(void *d_dst, const void *d_src, size_t bytes, int reps, 
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return KG_E_HIP;
     const long n16 = (long)(bytes / 16);
-    const unsigned grid = 256 * 8 * 4;
+    const unsigned grid = 256 * 128;
     hipLaunchKernelGGL(k_copy, dim3(grid), dim3(256), 0, st, (uint4 *)d_dst, (const uint4 *)d_src, n16);
     (void)hipEventRecord(e0, st);
     for (int i = 0; i < reps; ++i)

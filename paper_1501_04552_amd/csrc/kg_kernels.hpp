@@ -158,9 +158,9 @@ __global__ __launch_bounds__(256) void k_xpass(XArgs<T> a)
             const int k = t + j * TPL;
             const int m = k <= NH ? k : N - k;
             cx<T> x1 = mk<T>(0, 0), x2 = mk<T>(0, 0);
-            if (act) {
-                x1 = ld_nt(q1 + m);
-                x2 = ld_nt(q2 + m);
+            if (act) {  // each value is read twice (as X[k] and as conj X[N-k]): cached loads
+                x1 = q1[m];
+                x2 = q2[m];
             }
             if (k == 0 || k == NH) {
                 x1.im = 0;
@@ -542,11 +542,25 @@ __global__ __launch_bounds__(RSUB) void k_finalize(const double *sub, Rec *rec, 
     }
 }
 
-// Plain copy (calibration of bandwidth counters): 16 bytes per thread per pass.
+// Plain copy (bandwidth ceiling and counter calibration): every byte read and
+// written once, four 16-byte values in flight per thread, streaming hints.
 __global__ __launch_bounds__(256) void k_copy(uint4 *dst, const uint4 *src, long n16)
 {
-    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n16; i += (long)gridDim.x * 256)
-        dst[i] = src[i];
+    typedef unsigned v4u __attribute__((ext_vector_type(4)));
+    const long stride = (long)gridDim.x * 256 * 4;
+    for (long b = (long)blockIdx.x * 256 * 4 + threadIdx.x; b < n16; b += stride) {
+        v4u r[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const long i = b + (long)u * 256;
+            if (i < n16) r[u] = __builtin_nontemporal_load(reinterpret_cast<const v4u *>(src) + i);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const long i = b + (long)u * 256;
+            if (i < n16) __builtin_nontemporal_store(r[u], reinterpret_cast<v4u *>(dst) + i);
+        }
+    }
 }
 
 }  // namespace kg

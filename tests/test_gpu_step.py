@@ -197,3 +197,22 @@ def test_uniform_recurrence_at_512(kg):
         u = s.u()
     assert np.ptp(u) <= 1e-12
     assert abs(u[0, 0, 0] - ref["u"][0, 0, 0]) <= 1e-12 * abs(ref["u"][0, 0, 0])
+
+
+def test_graph_replays_match_single_step_launches(kg):
+    """Runs of >= 8 steps replay captured graphs; single steps launch eagerly.
+    Both paths must give the same bits, across several replays with eager work
+    and synchronisation in between."""
+    n, dt = 32, 0.01
+    u0 = ki.gaussian(n, 1.5, (0.9, 1.1, 1.3))
+    with kg.Solver(n, dt) as a, kg.Solver(n, dt) as b:
+        a.set_state(u0)
+        b.set_state(u0)
+        for rep in range(3):
+            for _ in range(16):
+                a.step(1)
+            b.step(16)
+            assert a.stats()[0] == b.stats()[0] == 16 * (rep + 1)
+            assert np.array_equal(a.u(), b.u())
+            assert a.energy() == b.energy()
+        assert np.array_equal(a.records(0, 48)[0], b.records(0, 48)[0])
