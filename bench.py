@@ -88,42 +88,57 @@ def main():
     n, dt = args.n, args.dt
     u0 = ki.gaussian(n, args.amplitude)
     u0_dev = torch.from_numpy(u0).cuda()
-    solver = kg.Solver(n, dt, blowup_threshold=1e3)
-    solver.set_state(u0_dev)
-    E0, _ = solver.energy()
 
-    st, _ = solver.step(args.warmup, sync=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    st, _ = kg.kg_step(solver.plan, args.steps, 0)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    elapsed = t1 - t0
-    done, blown, _ = solver.stats()
-    if blown:
-        raise RuntimeError("the benchmark run blew up")
+    def timed_run(precision):
+        """Warm up, time args.steps steps (graph replays), then an event-timed
+        run of the same length for per-kernel durations."""
+        solver = kg.Solver(n, dt, blowup_threshold=1e3, precision=precision)
+        solver.set_state(u0_dev)
+        E0, _ = solver.energy()
+        solver.step(args.warmup, sync=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        kg.kg_step(solver.plan, args.steps, 0)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        done, blown, _ = solver.stats()
+        if blown:
+            raise RuntimeError("the benchmark run blew up")
+        elin, q4, _ = solver.records(0, done)
+        series = [(m, float(elin[m] - (q4[m] + q4[m + 1]) / 8.0))
+                  for m in range(0, done - 1, args.energy_every)]
+        E_end, _ = solver.energy()
+        kg.kg_step(solver.plan, args.steps, kg.KG_STEP_TIMED)
+        ms, _ = kg.kg_kernel_times(solver.plan)
+        kbytes = [kg.kg_kernel_bytes(solver.plan, i) for i in range(4)]
+        solver.close()
+        return dict(elapsed=elapsed, series=series, drift=abs(E_end - E0) / abs(E0), ms=ms,
+                    kbytes=kbytes)
 
-    # energy every `energy_every` levels of the run so far (E^{m+1/2} from the records)
-    total = done
-    elin, q4, _ = solver.records(0, total)
-    E_series = [(m, float(elin[m] - (q4[m] + q4[m + 1]) / 8.0))
-                for m in range(0, total - 1, args.energy_every)]
-    E_end, _ = solver.energy()
-    for m, e in E_series:
+    r64 = timed_run(kg.KG_FP64)
+    r32 = timed_run(kg.KG_FP32)
+    for m, e in r64["series"]:
         print(f"step {m:5d}  E^(m+1/2) = {e:.15e}", file=sys.stderr)
-    drift = abs(E_end - E0) / abs(E0)
-
-    # per-kernel durations, HIP events around every launch of timed steps
-    st, _ = kg.kg_step(solver.plan, args.steps, kg.KG_STEP_TIMED)
-    ms, nt = kg.kg_kernel_times(solver.plan)
+    elapsed, drift, ms = r64["elapsed"], r64["drift"], r64["ms"]
     zi = kg.KERNELS.index("z_update")
-    zbytes = kg.kg_kernel_bytes(solver.plan, zi)
+    zbytes = r64["kbytes"][zi]
     z_gbs = zbytes / (ms[zi] * 1e-3) / 1e9
-    kernels = {name: {"ms": ms[i], "GB/s": (kg.kg_kernel_bytes(solver.plan, i) / (ms[i] * 1e-3) / 1e9
+    kernels = {name: {"ms": ms[i], "GB/s": (r64["kbytes"][i] / (ms[i] * 1e-3) / 1e9
                                             if i < 4 and ms[i] > 0 else None)}
                for i, name in enumerate(kg.KERNELS)}
-    solver.close()
 
+    # precision study: A = 1.5, sigma = 1, dt = 0.005, 200 steps, FP32 vs FP64
+    ua = ki.gaussian(n, 1.5)
+    res = {}
+    for prec in (kg.KG_FP64, kg.KG_FP32):
+        with kg.Solver(n, dt, precision=prec) as s:
+            s.set_state(ua)
+            Ea, _ = s.energy()
+            s.step(200)
+            res[prec] = (s.u(), abs(s.energy()[0] - Ea) / abs(Ea))
+    rel32 = float(np.linalg.norm(res[1][0] - res[0][0]) / np.linalg.norm(res[0][0]))
+    drift_a = {"fp64": res[0][1], "fp32": res[1][1]}
+    del ua, res
     # achievable-bandwidth ceiling: the library's plain copy kernel, 1 GiB
     nb = 1 << 30
     src = torch.empty(nb, dtype=torch.uint8, device="cuda")
@@ -136,6 +151,17 @@ def main():
     steps_per_s = args.steps / elapsed
     sweep = n * n * (n // 2 + 1) * 16
     step_bytes = 11 * sweep
+    t32 = r32["elapsed"] / args.steps
+    fp32 = {"steps_per_s": 1.0 / t32, "ms_per_step": 1e3 * t32,
+            "speedup_vs_fp64": (1.0 / t32) / steps_per_s,
+            "step_model_GBs": 12 * sweep / 2 / t32 / 1e9,
+            "step_hbm_frac": 12 * sweep / 2 / t32 / 1e9 / HBM_PEAK_GBS,
+            "kernels_ms": dict(zip(kg.KERNELS, r32["ms"])),
+            "energy_drift": r32["drift"],
+            "precision_study": {"workload": f"{n}^3 A=1.5 sigma=1 dt={dt} 200 steps",
+                                "rel_l2_fp32_vs_fp64": rel32,
+                                "energy_drift_fp64": drift_a["fp64"],
+                                "energy_drift_fp32": drift_a["fp32"]}}
     line = {
         "metric": "512^3 time steps/s (FP64)" if n == 512 else f"{n}^3 time steps/s (FP64)",
         "value": steps_per_s,
@@ -161,6 +187,7 @@ def main():
         "kernels": kernels,
         "copy_GBs": copy_gbs,
         "energy_drift": drift,
+        "fp32": fp32,
     }
     if not args.no_cpu_baseline and n <= 512:
         line["cpu_baseline"] = cpu_baseline(u0, dt)

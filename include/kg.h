@@ -57,7 +57,9 @@ typedef struct {
     int n;                   /* grid points per axis: a power of two, 8..512 */
     double L;                /* box length per axis; <= 0 selects 8*pi */
     double dt;               /* time step, > 0 */
-    int precision;           /* KG_FP64; KG_FP32 is reserved (KG_E_INVALID) */
+    int precision;           /* KG_FP64, or KG_FP32: FP32 transforms and cubic term, FP64
+                                update arithmetic and reductions, FP32 levels stored as
+                                v^n and v^n - v^{n-1} */
     int linear_only;         /* nonzero drops the cubic term (linear KG equation) */
     double blowup_threshold; /* max|u| above this is a blow-up; <= 0 disables the test */
 } kg_params;

@@ -29,11 +29,15 @@ using Plan = kg_plan_s;
 // Kernel launchers for one (precision, grid size, tile width).
 struct Ops {
     virtual ~Ops() = default;
-    virtual void x(Plan &pl, int mode, const double *rin, double *rout, double chi) = 0;
+    virtual void x(Plan &pl, int mode, const double *rin, double *rout, double chi,
+                   const double *rin2 = nullptr) = 0;
     virtual void y(Plan &pl, int dir, bool check_flag) = 0;
-    virtual void z(Plan &pl, int mode, void *Sp, const void *Sc, double scale, int has_vel) = 0;
+    virtual void z(Plan &pl, int mode, void *Sp, void *Sc, double scale, int has_vel,
+                   const void *Ssub = nullptr) = 0;
     virtual void pair_energy(Plan &pl, const void *S0, const void *S1) = 0;
-    virtual void state_to_spec(Plan &pl, const void *S, double *out) = 0;
+    virtual void state_to_spec(Plan &pl, const void *S, const void *Ssub, double *out) = 0;
+    virtual void q_to_spec(Plan &pl, double *out) = 0;
+    virtual void spec_to_q(Plan &pl, const double *in) = 0;
     virtual long x_blocks() const = 0;
     virtual long z_blocks(int ntx) const = 0;
 };
@@ -78,12 +82,14 @@ struct OpsImpl final : Ops {
     long x_blocks() const override { return XCfg<N>::blocks(); }
     long z_blocks(int ntx) const override { return yz_grid(ntx); }
 
-    void x(Plan &pl, int mode, const double *rin, double *rout, double chi) override
+    void x(Plan &pl, int mode, const double *rin, double *rout, double chi,
+           const double *rin2) override
     {
         XArgs<T> a;
         a.Q = (cx<T> *)pl.Q;
         a.tw = (const cx<T> *)pl.tw;
         a.rin = rin;
+        a.rin2 = rin2;
         a.rout = rout;
         a.part = pl.partA;
         a.ctl = pl.ctl;
@@ -112,13 +118,15 @@ struct OpsImpl final : Ops {
         else
             hipLaunchKernelGGL((k_ypass<T, N, W, 1>), g, b, 0, pl.stream, a);
     }
-    void z(Plan &pl, int mode, void *Sp, const void *Sc, double scale, int has_vel) override
+    void z(Plan &pl, int mode, void *Sp, void *Sc, double scale, int has_vel,
+           const void *Ssub) override
     {
         ZArgs<T> a;
         a.Q = (cx<T> *)pl.Q;
         a.tw = (const cx<T> *)pl.tw;
         a.Sp = (cx<T> *)Sp;
-        a.Sc = (const cx<T> *)Sc;
+        a.Sc = (cx<T> *)Sc;
+        a.Ssub = (const cx<T> *)Ssub;
         a.part = pl.partC;
         a.ctl = pl.ctl;
         a.P = pl.P;
@@ -145,43 +153,59 @@ struct OpsImpl final : Ops {
                            (const cx<T> *)S0, (const cx<T> *)S1, pl.partC, pl.H, pl.ntx, pl.ks2,
                            pl.p.dt);
     }
-    void state_to_spec(Plan &pl, const void *S, double *out) override
+    void state_to_spec(Plan &pl, const void *S, const void *Ssub, double *out) override
     {
         hipLaunchKernelGGL((k_state_to_spec<T, N, W>), dim3(2048), dim3(256), 0, pl.stream,
-                           (const cx<T> *)S, out, pl.H, pl.ntx);
+                           (const cx<T> *)S, (const cx<T> *)Ssub, out, pl.H, pl.ntx);
+    }
+    void q_to_spec(Plan &pl, double *out) override
+    {
+        hipLaunchKernelGGL((k_q_to_spec<T>), dim3(2048), dim3(256), 0, pl.stream,
+                           (const cx<T> *)pl.Q, out, pl.P, pl.H, (long)N * N);
+    }
+    void spec_to_q(Plan &pl, const double *in) override
+    {
+        hipLaunchKernelGGL((k_spec_to_q<T>), dim3(2048), dim3(256), 0, pl.stream, in,
+                           (cx<T> *)pl.Q, pl.P, pl.H, (long)N * N);
     }
 };
 
-// Tile width of the y and z passes: W columns of 16-byte complex values give
-// 16*W-byte row segments per wavefront access.  Whole 128-byte lines (W = 8)
-// stream at 5.5 TB/s where 64-byte segments reach 4.5 (measured at 512^3);
-// KG_TILE_W (4 or 8) overrides the default for experiments.
-int tile_width(int /*n*/)
+// Tile width of the y and z passes: W complex columns give 16*W-byte (FP64)
+// or 8*W-byte (FP32) row segments per wavefront access.  Whole 128-byte
+// lines stream at 5.5 TB/s where 64-byte segments reach 4.5 (measured at
+// 512^3 FP64).  KG_TILE_W overrides the default for experiments.
+int tile_width(int precision)
 {
+    const int def = precision == KG_FP32 ? 16 : 8;
     const char *e = std::getenv("KG_TILE_W");
-    if (e && (std::atoi(e) == 4 || std::atoi(e) == 8)) return std::atoi(e);
-    return 8;
+    if (e) {
+        const int w = std::atoi(e);
+        if ((precision == KG_FP64 && (w == 4 || w == 8)) || (precision == KG_FP32 && (w == 8 || w == 16)))
+            return w;
+    }
+    return def;
 }
 
-template <int W>
+template <typename T, int W>
 std::unique_ptr<Ops> make_ops_w(int n)
 {
     switch (n) {
-    case 8: return std::make_unique<OpsImpl<double, 8, W>>();
-    case 16: return std::make_unique<OpsImpl<double, 16, W>>();
-    case 32: return std::make_unique<OpsImpl<double, 32, W>>();
-    case 64: return std::make_unique<OpsImpl<double, 64, W>>();
-    case 128: return std::make_unique<OpsImpl<double, 128, W>>();
-    case 256: return std::make_unique<OpsImpl<double, 256, W>>();
-    case 512: return std::make_unique<OpsImpl<double, 512, W>>();
+    case 8: return std::make_unique<OpsImpl<T, 8, W>>();
+    case 16: return std::make_unique<OpsImpl<T, 16, W>>();
+    case 32: return std::make_unique<OpsImpl<T, 32, W>>();
+    case 64: return std::make_unique<OpsImpl<T, 64, W>>();
+    case 128: return std::make_unique<OpsImpl<T, 128, W>>();
+    case 256: return std::make_unique<OpsImpl<T, 256, W>>();
+    case 512: return std::make_unique<OpsImpl<T, 512, W>>();
     default: return nullptr;
     }
 }
 
 std::unique_ptr<Ops> make_ops(int n, int precision, int W)
 {
-    if (precision != KG_FP64) return nullptr;
-    return W == 8 ? make_ops_w<8>(n) : make_ops_w<4>(n);
+    if (precision == KG_FP64) return W == 4 ? make_ops_w<double, 4>(n) : make_ops_w<double, 8>(n);
+    if (precision == KG_FP32) return W == 8 ? make_ops_w<float, 8>(n) : make_ops_w<float, 16>(n);
+    return nullptr;
 }
 
 bool size_ok(int n) { return n >= 8 && n <= 512 && (n & (n - 1)) == 0; }
@@ -194,12 +218,12 @@ struct Layout {
 
 bool layout(const kg_params *p, Layout &lo)
 {
-    if (!p || !size_ok(p->n) || p->precision != KG_FP64) return false;
+    if (!p || !size_ok(p->n) || (p->precision != KG_FP64 && p->precision != KG_FP32)) return false;
     lo.n = p->n;
     lo.H = p->n / 2 + 1;
-    lo.W = tile_width(p->n);
+    lo.W = tile_width(p->precision);
     lo.ntx = (lo.H + lo.W - 1) / lo.W;
-    lo.esz = 16;
+    lo.esz = p->precision == KG_FP32 ? 8 : 16;
     // kx rows padded to whole 128-byte lines and to whole tiles
     const int per_line = (int)(128 / lo.esz);
     lo.P = ((lo.ntx * lo.W + per_line - 1) / per_line) * per_line;
@@ -270,28 +294,6 @@ kg_status to_device(kg_plan_s *pl, const double *src, int on_device, DevField &f
     return KG_OK;
 }
 
-// Working field Q (pitch P) <-> half spectrum of doubles (pitch H).
-__global__ void k_q_to_spec(const double2 *Q, double *out, int P, int H, long rows)
-{
-    const long total = rows * H;
-    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < total; i += (long)gridDim.x * 256) {
-        const long r = i / H;
-        const int k = (int)(i % H);
-        const double2 v = Q[r * P + k];
-        out[2 * i] = v.x;
-        out[2 * i + 1] = v.y;
-    }
-}
-__global__ void k_spec_to_q(const double *in, double2 *Q, int P, int H, long rows)
-{
-    const long total = rows * P;
-    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < total; i += (long)gridDim.x * 256) {
-        const long r = i / P;
-        const int k = (int)(i % P);
-        Q[i] = k < H ? make_double2(in[2 * (r * H + k)], in[2 * (r * H + k) + 1]) : make_double2(0, 0);
-    }
-}
-
 // Half spectrum (host or device) -> Q, and back.
 kg_status spec_in(kg_plan_s *pl, const double *spec, int on_device)
 {
@@ -301,8 +303,7 @@ kg_status spec_in(kg_plan_s *pl, const double *spec, int on_device)
         HIPCHK(pl, hipMalloc((void **)&d, bytes));
         HIPCHK(pl, hipMemcpyAsync(d, spec, bytes, hipMemcpyHostToDevice, pl->stream));
     }
-    hipLaunchKernelGGL(k_spec_to_q, dim3(2048), dim3(256), 0, pl->stream, d, (double2 *)pl->Q,
-                       pl->P, pl->H, (long)pl->n * pl->n);
+    pl->ops->spec_to_q(*pl, d);
     LAUNCHCHK(pl);
     if (!on_device) {
         HIPCHK(pl, hipStreamSynchronize(pl->stream));
@@ -316,8 +317,7 @@ kg_status spec_out(kg_plan_s *pl, double *spec, int on_device)
     const size_t bytes = (size_t)pl->n * pl->n * pl->H * 16;
     double *d = spec;
     if (!on_device) HIPCHK(pl, hipMalloc((void **)&d, bytes));
-    hipLaunchKernelGGL(k_q_to_spec, dim3(2048), dim3(256), 0, pl->stream, (const double2 *)pl->Q,
-                       d, pl->P, pl->H, (long)pl->n * pl->n);
+    pl->ops->q_to_spec(*pl, d);
     LAUNCHCHK(pl);
     if (!on_device) {
         HIPCHK(pl, hipMemcpyAsync(spec, d, bytes, hipMemcpyDeviceToHost, pl->stream));
@@ -345,20 +345,49 @@ void finalize(Plan &p, int nC, double thr, int mode)
 
 // Q <- inverse z and y transforms of level S (scaled by 1/M): what the x pass
 // of the next step expects.
-kg_status prepare_q(kg_plan_s *pl, const void *S)
+kg_status prepare_q(kg_plan_s *pl, const void *S, const void *Ssub = nullptr)
 {
     Plan &p = P(pl);
-    p.ops->z(p, Z_INV_STATE, nullptr, S, p.invM, 0);
+    p.ops->z(p, Z_INV_STATE, nullptr, const_cast<void *>(S), p.invM, 0, Ssub);
     p.ops->y(p, 1, false);
     LAUNCHCHK(pl);
     return KG_OK;
 }
 
+bool increment(const Plan &p) { return p.p.precision == KG_FP32; }
+
+// State buffers the step from level m reads and writes: (v^m, v^{m-1})
+// alternate between S[0] and S[1] for FP64; FP32 keeps (v, Delta) in place.
+void step_levels(Plan &p, long m, void *&Sc, void *&Sp)
+{
+    if (increment(p)) {
+        Sc = p.S[0];
+        Sp = p.S[1];
+    } else {
+        Sc = p.S[m & 1];
+        Sp = p.S[(m + 1) & 1];
+    }
+}
+
+// The stored level v^{n-back} (back = 0 or 1) after the control block `c`,
+// as a buffer S minus an optional Ssub.  After a blow-up at level n the FP32
+// buffers hold v^{n+1} and Delta^{n+1}, so v^n = v - Delta.
+void stored_level(Plan &p, const Ctl &c, int back, const void *&S, const void *&Ssub)
+{
+    Ssub = nullptr;
+    if (increment(p)) {
+        S = p.S[0];
+        if (c.flag || back == 1) Ssub = p.S[1];
+    } else {
+        S = p.S[(c.step - back) & 1];
+    }
+}
+
 // One forward 3D r2c transform of a real field into Q (x, then y; the z
 // transform is done by the caller's z-pass mode).
-void forward_xy(Plan &p, const double *d_real, bool cube)
+void forward_xy(Plan &p, const double *d_real, bool cube, const double *d_minus = nullptr)
 {
-    p.ops->x(p, X_R2C, d_real, nullptr, cube ? 1.0 : 0.0);
+    p.ops->x(p, X_R2C, d_real, nullptr, cube ? 1.0 : 0.0, d_minus);
     p.ops->y(p, -1, false);
 }
 
@@ -399,7 +428,6 @@ kg_status kg_plan(const kg_params *p, void *d_workspace, size_t ws_bytes, void *
     *out = nullptr;
     if (!(p->dt > 0) || !std::isfinite(p->dt)) return KG_E_INVALID;
     if (p->precision != KG_FP64 && p->precision != KG_FP32) return KG_E_INVALID;
-    if (p->precision == KG_FP32) return KG_E_INVALID;
     if (!size_ok(p->n)) return KG_E_UNSUPPORTED_SIZE;
     Layout lo;
     if (!layout(p, lo)) return KG_E_INVALID;
@@ -461,16 +489,22 @@ kg_status kg_plan(const kg_params *p, void *d_workspace, size_t ws_bytes, void *
     c += lo.rec;
     pl->ctl = (Ctl *)c;
 
-    // Twiddle table exp(-2 pi i j / n), each entry from cos/sin in double.
+    // Twiddle table exp(-2 pi i j / n), each entry from cos/sin in double
+    // (rounded once to float for the FP32 path).
     std::vector<double> tw(2 * (size_t)pl->n);
+    std::vector<float> twf(2 * (size_t)pl->n);
     for (int j = 0; j < pl->n; ++j) {
         const double ang = 2.0 * M_PI * (double)j / (double)pl->n;
         tw[2 * j] = std::cos(ang);
         tw[2 * j + 1] = -std::sin(ang);
+        twf[2 * j] = (float)tw[2 * j];
+        twf[2 * j + 1] = (float)tw[2 * j + 1];
     }
     Ctl c0{};
     c0.blow_step = -1;
-    hipError_t e = hipMemcpyAsync(pl->tw, tw.data(), tw.size() * sizeof(double),
+    const bool f32 = p->precision == KG_FP32;
+    hipError_t e = hipMemcpyAsync(pl->tw, f32 ? (const void *)twf.data() : (const void *)tw.data(),
+                                  tw.size() * (f32 ? sizeof(float) : sizeof(double)),
                                   hipMemcpyHostToDevice, pl->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(pl->ctl, &c0, sizeof(Ctl), hipMemcpyHostToDevice, pl->stream);
@@ -511,7 +545,8 @@ kg_status kg_set_state(kg_plan_t *plan, const double *u0, const double *aux, int
     Ctl c0{};
     c0.blow_step = -1;
     HIPCHK(plan, hipMemcpyAsync(p.ctl, &c0, sizeof(Ctl), hipMemcpyHostToDevice, p.stream));
-    // v^m lives in S[m % 2]: v^0 -> S[0], v^{-1} -> S[1].
+    // FP64: v^m lives in S[m % 2] (v^0 -> S[0], v^{-1} -> S[1]).
+    // FP32: S[0] = v^0, S[1] = Delta^0 = v^0 - v^{-1}.
     void *S0 = p.S[0], *S1 = p.S[1];
     if (mode == KG_INIT_VELOCITY) {
         if (p.chi != 0.0) {  // N^0 = F[u0^3] -> S1
@@ -525,13 +560,21 @@ kg_status kg_set_state(kg_plan_t *plan, const double *u0, const double *aux, int
     } else {
         forward_xy(p, du0.d, false);
         p.ops->z(p, Z_FWD_STATE, S0, nullptr, 1.0, 0);
-        forward_xy(p, daux.d, false);
+        if (increment(p))
+            forward_xy(p, du0.d, false, daux.d);  // F[u^0 - u^{-1}]
+        else
+            forward_xy(p, daux.d, false);
         p.ops->z(p, Z_FWD_STATE, S1, nullptr, 1.0, 0);
     }
     LAUNCHCHK(plan);
     // Energy of the initial pair: linear part of (v^{-1}, v^0) and Q4 of u^{-1}.
-    p.ops->pair_energy(p, S1, S0);
-    if ((s = prepare_q(plan, S1)) != KG_OK) return s;
+    if (increment(p)) {
+        p.ops->pair_energy(p, S0, S1);
+        if ((s = prepare_q(plan, S0, S1)) != KG_OK) return s;
+    } else {
+        p.ops->pair_energy(p, S1, S0);
+        if ((s = prepare_q(plan, S1)) != KG_OK) return s;
+    }
     p.ops->x(p, X_REDUCE, nullptr, nullptr, 0.0);
     finalize(p, PAIR_BLOCKS, 0.0, 2);
     LAUNCHCHK(plan);
@@ -549,7 +592,8 @@ namespace {
 // Enqueue the kernels of step m (levels v^{m-1}, v^m -> v^{m+1}) on stream st.
 void enqueue_step(Plan &p, long m, hipStream_t st)
 {
-    void *Sc = p.S[m & 1], *Sp = p.S[(m + 1) & 1];
+    void *Sc, *Sp;
+    step_levels(p, m, Sc, Sp);
     hipStream_t keep = p.stream;
     p.stream = st;
     p.ops->x(p, X_STEP, nullptr, nullptr, p.chi);
@@ -627,7 +671,8 @@ kg_status kg_step(kg_plan_t *plan, int nsteps, unsigned flags, int *steps_done)
     }
     for (int i = 0; i < nsteps; ++i) {
         const long m = p.steps + i;
-        void *Sc = p.S[m & 1], *Sp = p.S[(m + 1) & 1];
+        void *Sc, *Sp;
+        step_levels(p, m, Sc, Sp);
         hipEvent_t *ev = timed ? &p.tev[(size_t)6 * i] : nullptr;
         if (timed) HIPCHK(plan, hipEventRecord(ev[0], p.stream));
         p.ops->x(p, X_STEP, nullptr, nullptr, p.chi);
@@ -748,7 +793,9 @@ kg_status kg_get_u(kg_plan_t *plan, double *u_out, int on_device)
     Ctl c;
     kg_status s = read_ctl(plan, c);
     if (s != KG_OK) return s;
-    if ((s = prepare_q(plan, p.S[c.step & 1])) != KG_OK) return s;
+    const void *S, *Ssub;
+    stored_level(p, c, 0, S, Ssub);
+    if ((s = prepare_q(plan, S, Ssub)) != KG_OK) return s;
     const size_t bytes = (size_t)p.n * p.n * p.n * sizeof(double);
     double *d = u_out;
     if (!on_device) HIPCHK(plan, hipMalloc((void **)&d, bytes));
@@ -772,12 +819,14 @@ kg_status kg_get_spectrum(kg_plan_t *plan, int which, double *out, int on_device
     Ctl c;
     kg_status s = read_ctl(plan, c);
     if (s != KG_OK) return s;
-    const int level = c.step - which;
-    const void *S = p.S[level & 1];
+    if (increment(p) && c.flag && which == 1)
+        return fail(plan, KG_E_INVALID, "the FP32 state keeps no level before a blown one");
+    const void *S, *Ssub;
+    stored_level(p, c, which, S, Ssub);
     const size_t bytes = (size_t)p.n * p.n * p.H * 16;
     double *d = out;
     if (!on_device) HIPCHK(plan, hipMalloc((void **)&d, bytes));
-    p.ops->state_to_spec(p, S, d);
+    p.ops->state_to_spec(p, S, Ssub, d);
     LAUNCHCHK(plan);
     if (!on_device) {
         HIPCHK(plan, hipMemcpyAsync(out, d, bytes, hipMemcpyDeviceToHost, p.stream));
@@ -852,7 +901,9 @@ kg_status kg_load_state(kg_plan_t *plan, const void *host_buf, size_t bytes)
     HIPCHK(plan, hipMemcpy(p.ctl, &c, sizeof c, hipMemcpyHostToDevice));
     if (c.step > 0)
         HIPCHK(plan, hipMemcpy(p.rec + ((c.step - 1) & (RING - 1)), &r, sizeof r, hipMemcpyHostToDevice));
-    kg_status s = prepare_q(plan, p.S[c.step & 1]);
+    const void *S, *Ssub;
+    stored_level(p, c, 0, S, Ssub);
+    kg_status s = prepare_q(plan, S, Ssub);
     if (s != KG_OK) return s;
     HIPCHK(plan, hipStreamSynchronize(p.stream));
     p.steps = c.step;
@@ -931,8 +982,8 @@ kg_status kg_debug_time_kernel(kg_plan_t *plan, int kernel, int reps, float *ms)
     hipEvent_t e0, e1;
     HIPCHK(plan, hipEventCreate(&e0));
     HIPCHK(plan, hipEventCreate(&e1));
-    const long m = p.steps;
-    void *Sc = p.S[m & 1], *Sp = p.S[(m + 1) & 1];
+    void *Sc, *Sp;
+    step_levels(p, p.steps, Sc, Sp);
     auto launch = [&]() {
         switch (kernel) {
         case 0: p.ops->x(p, X_STEP, nullptr, nullptr, p.chi); break;
@@ -984,7 +1035,8 @@ double kg_kernel_bytes(const kg_plan_t *plan, int kernel)
     if (!plan || kernel < 0 || kernel > 3) return 0.0;
     // one sweep = every half-spectrum value once
     const double sweep = (double)plan->n * plan->n * plan->H * (double)plan->esz;
-    return kernel == 2 ? 5.0 * sweep : 2.0 * sweep;
+    const double zsweeps = plan->p.precision == KG_FP32 ? 6.0 : 5.0;  // + Delta read/write
+    return kernel == 2 ? zsweeps * sweep : 2.0 * sweep;
 }
 
 }  // extern "C"

@@ -99,6 +99,7 @@ struct XArgs {
     cx<T> *Q;
     const cx<T> *tw;      // exp(-2 pi i j / n), j < n
     const double *rin;    // X_R2C: real input [z][y][x]
+    const double *rin2;   // X_R2C: if set, the input is rin - rin2
     double *rout;         // X_C2R: real output
     double *part;         // X_STEP / X_REDUCE: (max|u|, sum u^4) per workgroup
     const Ctl *ctl;
@@ -144,7 +145,12 @@ __global__ __launch_bounds__(256) void k_xpass(XArgs<T> a)
 #pragma unroll
         for (int j = 0; j < E; ++j) {
             const int m = t + j * TPL;
-            T x1 = act ? (T)s1[m] : (T)0, x2 = act ? (T)s2[m] : (T)0;
+            double d1 = act ? s1[m] : 0.0, d2 = act ? s2[m] : 0.0;
+            if (a.rin2 && act) {
+                d1 -= a.rin2[(2 * pr) * N + m];
+                d2 -= a.rin2[(2 * pr + 1) * N + m];
+            }
+            T x1 = (T)d1, x2 = (T)d2;
             if (a.chi != (T)0) {
                 x1 = x1 * x1 * x1;
                 x2 = x2 * x2 * x2;
@@ -282,12 +288,22 @@ enum ZMode {
     Z_START = 5       // symmetric start: Sp = (alpha/2) Sc - dt Fz(Q) + (beta/2) chi Sp
 };
 
+// Time levels.  FP64 keeps two levels, v^n and v^{n-1} (Sp holds v^{n-1} and
+// receives v^{n+1}).  FP32 stores the increment form v^n (Sc) and
+// Delta^n = v^n - v^{n-1} (Sp), both updated in place, with the update done in
+// FP64: rounding a stored pair of nearly equal FP32 levels would amplify by
+// about 1/(omega dt), rounding their difference does not.
+template <typename T>
+constexpr bool increment_form() { return sizeof(T) == 4; }
+
 template <typename T>
 struct ZArgs {
     cx<T> *Q;
     const cx<T> *tw;
-    cx<T> *Sp;        // Z_STEP: v^{n-1} in, v^{n+1} out; Z_FWD_STATE: output; Z_START: N^0 in, v^{-1} out
-    const cx<T> *Sc;  // Z_STEP / Z_START: v^n; Z_INV_STATE: input level
+    cx<T> *Sp;        // Z_STEP: v^{n-1} (FP64) or Delta^n (FP32), updated; Z_FWD_STATE: output;
+                      // Z_START: N^0 in, v^{-1} (FP64) or Delta^0 (FP32) out
+    cx<T> *Sc;        // Z_STEP / Z_START: v^n (updated in place for FP32); Z_INV_STATE: input
+    const cx<T> *Ssub;  // Z_INV_STATE: if set, the input is Sc - Ssub
     double *part;     // Z_STEP: energy partial per workgroup
     const Ctl *ctl;
     int P, H, ntx;
@@ -364,10 +380,18 @@ __global__ __launch_bounds__((YZCfg<N, W>::NT)) void k_zpass(ZArgs<T> a)
                 const long si = sbase + (long)kz * W;
                 const cx<T> vc = a.Sc[si];
                 const cx<T> nl = a.chi != 0.0 ? a.Sp[si] : zero;
-                const double re = 0.5 * al * (double)vc.re - a.dt * (double)v[j].re +
-                                  0.5 * be * a.chi * (double)nl.re;
-                const double im = 0.5 * al * (double)vc.im - a.dt * (double)v[j].im +
-                                  0.5 * be * a.chi * (double)nl.im;
+                double re, im;
+                if constexpr (increment_form<T>()) {
+                    // Delta^0 = v^0 - v^{-1} = (2a/(1+a)) v^0 + dt F[u_t0] - (beta/2) chi N^0
+                    const double c0 = 1.0 - 0.5 * al;  // = 2a/(1+a), no cancellation for small a
+                    re = c0 * (double)vc.re + a.dt * (double)v[j].re - 0.5 * be * a.chi * (double)nl.re;
+                    im = c0 * (double)vc.im + a.dt * (double)v[j].im - 0.5 * be * a.chi * (double)nl.im;
+                } else {
+                    re = 0.5 * al * (double)vc.re - a.dt * (double)v[j].re +
+                         0.5 * be * a.chi * (double)nl.re;
+                    im = 0.5 * al * (double)vc.im - a.dt * (double)v[j].im +
+                         0.5 * be * a.chi * (double)nl.im;
+                }
                 a.Sp[si] = mk((T)re, (T)im);
             }
         }
@@ -386,21 +410,44 @@ __global__ __launch_bounds__((YZCfg<N, W>::NT)) void k_zpass(ZArgs<T> a)
                 coeffs(kx, my, mz, a.ks2, a.dt, al, be, w2);
                 const long si = sbase + (long)kz * W;
                 const cx<T> vc = ld_nt(a.Sc + si), vp = ld_nt(a.Sp + si);
-                const double re = al * (double)vc.re - (double)vp.re + be * (double)v[j].re;
-                const double im = al * (double)vc.im - (double)vp.im + be * (double)v[j].im;
-                nv = mk((T)re, (T)im);
-                st_nt(a.Sp + si, nv);
-                const double dr = (double)nv.re - (double)vc.re, di = (double)nv.im - (double)vc.im;
-                const double sr = (double)nv.re + (double)vc.re, sim = (double)nv.im + (double)vc.im;
+                double nr, ni, dr, di;  // v^{n+1} and v^{n+1} - v^n in FP64
+                if constexpr (increment_form<T>()) {
+                    // Delta^{n+1} = Delta^n - (2 - alpha) v^n + beta N^n
+                    const double c2 = 2.0 - al;
+                    dr = (double)vp.re - c2 * (double)vc.re + be * (double)v[j].re;
+                    di = (double)vp.im - c2 * (double)vc.im + be * (double)v[j].im;
+                    nr = (double)vc.re + dr;
+                    ni = (double)vc.im + di;
+                    nv = mk((T)nr, (T)ni);
+                    st_nt(a.Sc + si, nv);
+                    st_nt(a.Sp + si, mk((T)dr, (T)di));
+                } else {
+                    nr = al * (double)vc.re - (double)vp.re + be * (double)v[j].re;
+                    ni = al * (double)vc.im - (double)vp.im + be * (double)v[j].im;
+                    nv = mk((T)nr, (T)ni);
+                    st_nt(a.Sp + si, nv);
+                    dr = nr - (double)vc.re;
+                    di = ni - (double)vc.im;
+                }
+                const double sr = nr + (double)vc.re, sim = ni + (double)vc.im;
                 esum += wgt * ((dr * dr + di * di) * idt2 + 0.25 * w2 * (sr * sr + sim * sim));
             }
+            // the stored level, scaled as a resumed run scales it (Z_INV_STATE)
             v[j] = scale(nv, (T)a.scale);
         }
         __syncthreads();
     } else if constexpr (MODE == Z_INV_STATE) {
 #pragma unroll
-        for (int j = 0; j < E; ++j)
-            v[j] = act ? scale(a.Sc[sbase + (long)(t + j * TPL) * W], (T)a.scale) : zero;
+        for (int j = 0; j < E; ++j) {
+            const long si = sbase + (long)(t + j * TPL) * W;
+            if (act && a.Ssub) {
+                const cx<T> x = a.Sc[si], y = a.Ssub[si];
+                v[j] = mk((T)(((double)x.re - (double)y.re) * a.scale),
+                          (T)(((double)x.im - (double)y.im) * a.scale));
+            } else {
+                v[j] = act ? scale(a.Sc[si], (T)a.scale) : zero;
+            }
+        }
     } else if constexpr (MODE == Z_INV_Q) {
 #pragma unroll
         for (int j = 0; j < E; ++j) v[j] = act ? scale(g[(t + j * TPL) * zs], (T)a.scale) : zero;
@@ -417,6 +464,8 @@ __global__ __launch_bounds__((YZCfg<N, W>::NT)) void k_zpass(ZArgs<T> a)
 // Linear energy partials of a pair of levels stored in the state layout:
 // sum w_k [|v1 - v0|^2/dt^2 + omega_k^2 |v1 + v0|^2 / 4] (w_k = 1 on the kx = 0
 // and kx = n/2 planes, 2 elsewhere: the half spectrum stands for the full one).
+// S0 = v^{-1}, S1 = v^0 for two levels; S0 = v^0, S1 = Delta^0 for the
+// increment form.
 template <typename T, int N, int W>
 __global__ __launch_bounds__(256) void k_pair_energy(const cx<T> *S0, const cx<T> *S1, double *part,
                                                      int H, int ntx, double ks2, double dt)
@@ -436,16 +485,28 @@ __global__ __launch_bounds__(256) void k_pair_energy(const cx<T> *S0, const cx<T
         coeffs(kx, my, mz, ks2, dt, al, be, w2);
         const double wgt = (kx == 0 || kx == N / 2) ? 1.0 : 2.0;
         const cx<T> a0 = S0[i], a1 = S1[i];
-        const double dr = (double)a1.re - (double)a0.re, di = (double)a1.im - (double)a0.im;
-        const double sr = (double)a1.re + (double)a0.re, si = (double)a1.im + (double)a0.im;
+        double dr, di, sr, si;
+        if constexpr (increment_form<T>()) {
+            dr = (double)a1.re;
+            di = (double)a1.im;
+            sr = 2.0 * (double)a0.re - dr;
+            si = 2.0 * (double)a0.im - di;
+        } else {
+            dr = (double)a1.re - (double)a0.re;
+            di = (double)a1.im - (double)a0.im;
+            sr = (double)a1.re + (double)a0.re;
+            si = (double)a1.im + (double)a0.im;
+        }
         esum += wgt * ((dr * dr + di * di) * idt2 + 0.25 * w2 * (sr * sr + si * si));
     }
     block_max_sum<256>(0.0, esum, part + 2 * blockIdx.x);
 }
 
-// Gather a state-layout level into the half-spectrum layout [kz][ky][kx] (pitch H).
+// Gather a state-layout level (S, or S - Ssub when Ssub is set) into the
+// half-spectrum layout [kz][ky][kx] (pitch H) of doubles.
 template <typename T, int N, int W>
-__global__ __launch_bounds__(256) void k_state_to_spec(const cx<T> *S, double *out, int H, int ntx)
+__global__ __launch_bounds__(256) void k_state_to_spec(const cx<T> *S, const cx<T> *Ssub, double *out,
+                                                       int H, int ntx)
 {
     const long total = (long)N * N * H;
     for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < total; i += (long)gridDim.x * 256) {
@@ -453,8 +514,37 @@ __global__ __launch_bounds__(256) void k_state_to_spec(const cx<T> *S, double *o
         const int ky = (int)((i / H) % N);
         const int kz = (int)(i / ((long)H * N));
         const long si = (((long)ky * ntx + kx / W) * N + kz) * W + (kx % W);
-        out[2 * i] = (double)S[si].re;
-        out[2 * i + 1] = (double)S[si].im;
+        double re = (double)S[si].re, im = (double)S[si].im;
+        if (Ssub) {
+            re -= (double)Ssub[si].re;
+            im -= (double)Ssub[si].im;
+        }
+        out[2 * i] = re;
+        out[2 * i + 1] = im;
+    }
+}
+
+// Working field Q (pitch P) <-> half spectrum of doubles (pitch H).
+template <typename T>
+__global__ __launch_bounds__(256) void k_q_to_spec(const cx<T> *Q, double *out, int P, int H, long rows)
+{
+    const long total = rows * H;
+    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < total; i += (long)gridDim.x * 256) {
+        const long r = i / H;
+        const int k = (int)(i % H);
+        const cx<T> v = Q[r * P + k];
+        out[2 * i] = (double)v.re;
+        out[2 * i + 1] = (double)v.im;
+    }
+}
+template <typename T>
+__global__ __launch_bounds__(256) void k_spec_to_q(const double *in, cx<T> *Q, int P, int H, long rows)
+{
+    const long total = rows * P;
+    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < total; i += (long)gridDim.x * 256) {
+        const long r = i / P;
+        const int k = (int)(i % P);
+        Q[i] = k < H ? mk((T)in[2 * (r * H + k)], (T)in[2 * (r * H + k) + 1]) : mk<T>(0, 0);
     }
 }
 

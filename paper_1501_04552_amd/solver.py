@@ -13,6 +13,7 @@ class Solver:
 
     def __init__(self, n, dt, L=0.0, linear_only=False, blowup_threshold=0.0,
                  precision=_kg.KG_FP64):
+        """precision: KG_FP64 (0) or KG_FP32 (1)."""
         self.n = n
         self.params = _kg.make_params(n, dt, L, precision, linear_only, blowup_threshold)
         nbytes = _kg.kg_workspace_bytes(self.params)

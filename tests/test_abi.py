@@ -38,6 +38,10 @@ def test_host_side_validation():
                 kg.make_params(64, 0.0), kg.make_params(64, -1.0),
                 kg.make_params(64, 0.01, precision=7)):
         assert kg.kg_workspace_bytes(bad) == 0
+    # FP32 is accepted and needs about half the FP64 workspace
+    b64 = kg.kg_workspace_bytes(kg.make_params(256, 0.01))
+    b32 = kg.kg_workspace_bytes(kg.make_params(256, 0.01, precision=kg.KG_FP32))
+    assert 0.45 * b64 < b32 < 0.6 * b64
     # sizes of the stored fields: 3 complex fields of n*n*pitch plus small buffers
     b512 = kg.kg_workspace_bytes(kg.make_params(512, 0.005))
     assert 3 * 512 * 512 * 257 * 16 < b512 < 3.2 * 512 * 512 * 264 * 16
