@@ -54,7 +54,7 @@ enum { KG_INIT_VELOCITY = 0, KG_INIT_TWO_LEVEL = 1 };
 enum { KG_STEP_SYNC = 1u, KG_STEP_TIMED = 2u };
 
 typedef struct {
-    int n;                   /* grid points per axis: a power of two, 8..512 */
+    int n;                   /* grid points per axis: 2^a (8..512) or 3*2^a (24..384) */
     double L;                /* box length per axis; <= 0 selects 8*pi */
     double dt;               /* time step, > 0 */
     int precision;           /* KG_FP64, or KG_FP32: FP32 transforms and cubic term, FP64

@@ -190,6 +190,11 @@ template <typename T, int W>
 std::unique_ptr<Ops> make_ops_w(int n)
 {
     switch (n) {
+    case 24: return std::make_unique<OpsImpl<T, 24, W>>();
+    case 48: return std::make_unique<OpsImpl<T, 48, W>>();
+    case 96: return std::make_unique<OpsImpl<T, 96, W>>();
+    case 192: return std::make_unique<OpsImpl<T, 192, W>>();
+    case 384: return std::make_unique<OpsImpl<T, 384, W>>();
     case 8: return std::make_unique<OpsImpl<T, 8, W>>();
     case 16: return std::make_unique<OpsImpl<T, 16, W>>();
     case 32: return std::make_unique<OpsImpl<T, 32, W>>();
@@ -208,7 +213,13 @@ std::unique_ptr<Ops> make_ops(int n, int precision, int W)
     return nullptr;
 }
 
-bool size_ok(int n) { return n >= 8 && n <= 512 && (n & (n - 1)) == 0; }
+// Grid sizes: powers of two 8..512 and three times a power of two 24..384.
+bool size_ok(int n)
+{
+    const int b = (n % 3 == 0) ? n / 3 : n;
+    const bool pow2 = b > 0 && (b & (b - 1)) == 0;
+    return pow2 && ((n % 3 != 0 && n >= 8 && n <= 512) || (n % 3 == 0 && n >= 24 && n <= 384));
+}
 
 struct Layout {
     int n, H, W, ntx, P;

@@ -89,6 +89,15 @@ __device__ __forceinline__ void dft(cx<T> (&x)[R])
         cx<T> a = x[0], b = x[1];
         x[0] = a + b;
         x[1] = a - b;
+    } else if constexpr (R == 3) {
+        // w_3 = -1/2 + DIR i sqrt(3)/2
+        const T h = (T)0.86602540378443864676372317075293618347;
+        const cx<T> t1 = x[1] + x[2];
+        const cx<T> t2 = x[0] - scale(t1, (T)0.5);
+        const cx<T> t3 = scale(rot90<DIR>(x[1] - x[2]), h);
+        x[0] = x[0] + t1;
+        x[1] = t2 + t3;
+        x[2] = t2 - t3;
     } else if constexpr (R == 4) {
         cx<T> y0 = x[0] + x[2], y1 = x[0] - x[2];
         cx<T> y2 = x[1] + x[3], y3 = rot90<DIR>(x[1] - x[3]);
@@ -120,30 +129,42 @@ __device__ __forceinline__ void dft(cx<T> (&x)[R])
     }
 }
 
-// Radix plan of a line of NL points (power of two, 2 <= NL <= 4096): the first
-// stage takes the remainder radix (2 or 4) when log2(NL) is not a multiple of
-// 3, every other stage is radix 8.
+// Radix plan of a line of NL points.
+//   NL = 2^a (2 <= NL <= 4096): E = min(8, NL) values per thread; the first
+//     stage takes the remainder radix (2 or 4) when a is not a multiple of 3,
+//     every other stage is radix 8.
+//   NL = 3 * 2^a (12 <= NL <= 3072): E = 12; a radix-3 stage, then a radix-2
+//     stage when a is odd, then radix-4 stages.
+// Every radix divides E, which keeps thread t on positions {t + j*TPL}.
 template <int NL>
 struct Radix {
+    static constexpr bool THREE = (NL % 3 == 0);
+    static constexpr int BASE = THREE ? NL / 3 : NL;
     static constexpr int log2n()
     {
         int l = 0;
-        while ((1 << l) < NL) ++l;
+        while ((1 << l) < BASE) ++l;
         return l;
     }
-    static constexpr int E = NL >= 8 ? 8 : NL;
-    static constexpr int TPL = NL / E;
     static constexpr int LG = log2n();
-    static constexpr int REM = LG % 3;  // 0, 1 (radix 2) or 2 (radix 4)
-    static constexpr int NST = LG / 3 + (REM ? 1 : 0);
-    static constexpr int radix(int s) { return (REM && s == 0) ? (1 << REM) : 8; }
+    static constexpr int E = THREE ? 12 : (NL >= 8 ? 8 : NL);
+    static constexpr int TPL = NL / E;
+    static constexpr int REM = THREE ? (LG & 1) : LG % 3;
+    static constexpr int NST = THREE ? 1 + REM + LG / 2 : LG / 3 + (REM ? 1 : 0);
+    static constexpr int radix(int s)
+    {
+        if (THREE) return s == 0 ? 3 : (REM && s == 1) ? 2 : 4;
+        return (REM && s == 0) ? (1 << REM) : 8;
+    }
     static constexpr int lbefore(int s)
     {
         int l = 1;
         for (int q = 0; q < s; ++q) l *= radix(q);
         return l;
     }
-    static_assert((1 << LG) == NL, "line length must be a power of two");
+    static_assert((1 << LG) == BASE, "line length must be 2^a or 3 * 2^a");
+    static_assert(!THREE || NL >= 12, "3 * 2^a lines need at least 12 points");
+    static_assert(TPL * E == NL, "positions must divide evenly among threads");
 };
 
 // LDS slot of line position p: one padding slot after every 8 positions, so
@@ -175,6 +196,7 @@ template <int R, typename T>
 __device__ __forceinline__ void twiddles(cx<T> (&w)[R], const cx<T> *__restrict__ tw, int idx)
 {
     w[1] = tw[idx];
+    if constexpr (R == 3) w[2] = tw[2 * idx];
     if constexpr (R >= 4) {
         w[2] = tw[2 * idx];
         w[3] = cmul(w[1], w[2]);
@@ -209,7 +231,7 @@ __device__ __forceinline__ void fft_line(cx<T> (&v)[Radix<NL>::E], cx<T> *lds, i
 #pragma unroll
     for (int b = 0; b < E / R; ++b) {
         const int i = t + TPL * b;
-        const int k = i & (L - 1);
+        const int k = i % L;  // L is a compile-time constant
         cx<T> x[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) x[r] = v[b + r * (E / R)];

@@ -34,7 +34,10 @@ def test_host_side_validation():
     from paper_1501_04552_amd import kg
     assert kg.kg_status_str(kg.KG_BLOWUP) == "KG_BLOWUP"
     assert kg.kg_workspace_bytes(kg.make_params(64, 0.01)) > 0
-    for bad in (kg.make_params(48, 0.01), kg.make_params(1024, 0.01), kg.make_params(100, 0.01),
+    for good in (8, 24, 48, 96, 128, 384, 512):
+        assert kg.kg_workspace_bytes(kg.make_params(good, 0.01)) > 0
+    for bad in (kg.make_params(40, 0.01), kg.make_params(1024, 0.01), kg.make_params(100, 0.01),
+                kg.make_params(12, 0.01), kg.make_params(36, 0.01), kg.make_params(768, 0.01),
                 kg.make_params(64, 0.0), kg.make_params(64, -1.0),
                 kg.make_params(64, 0.01, precision=7)):
         assert kg.kg_workspace_bytes(bad) == 0
@@ -46,7 +49,7 @@ def test_host_side_validation():
     b512 = kg.kg_workspace_bytes(kg.make_params(512, 0.005))
     assert 3 * 512 * 512 * 257 * 16 < b512 < 3.2 * 512 * 512 * 264 * 16
     with pytest.raises(kg.KGError) as e:
-        kg.kg_plan(kg.make_params(48, 0.01))
+        kg.kg_plan(kg.make_params(40, 0.01))
     assert e.value.status == kg.KG_E_UNSUPPORTED_SIZE
     with pytest.raises(kg.KGError) as e:
         kg.kg_plan(kg.make_params(64, 0.0))

@@ -14,7 +14,7 @@ import oracle
 
 pytestmark = pytest.mark.gpu
 
-SIZES = [8, 16, 32, 64, 128, 256]
+SIZES = [8, 16, 24, 32, 48, 64, 96, 128, 256]
 TOL = 1e-13
 
 

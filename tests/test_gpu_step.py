@@ -50,6 +50,8 @@ def test_small_config_matches_oracle(kg):
 
 @pytest.mark.parametrize("n,A,sigma,steps", [(64, 1.5, (1.0, 1.0, 1.0), 100),
                                              (16, 1.2, (0.9, 1.1, 1.4), 100),
+                                             (48, 2.0, (0.7, 1.3, 1.0), 100),
+                                             (96, 1.5, (0.6, 0.9, 1.2), 60),
                                              (128, 1.0, (0.8, 1.0, 1.3), 30)])
 def test_nonlinear_gaussian_matches_oracle(kg, n, A, sigma, steps):
     dt = 0.005
