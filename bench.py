@@ -33,7 +33,47 @@ def parse():
     ap.add_argument("--amplitude", type=float, default=0.1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--energy-every", type=int, default=50)
+    ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--sweep-runs", type=int, default=512)
+    ap.add_argument("--sweep-seq-sample", type=int, default=16)
     return ap.parse_args()
+
+
+def sweep(args, kg, ki, torch):
+    """Batched parametric sweep: seeded runs over grid sizes {48, 64, 96, 128},
+    A ~ U[0.5, 4], sigma ~ U[0.5, 2] per axis, dt = 0.005, up to 2000 steps or
+    blow-up (max|u| > 1e3), against a sequential kg_step loop on a sample."""
+    import numpy as np
+    draws = ki.sweep_runs(args.sweep_runs, seed=0)
+    runs = [dict(n=d["n"], A=d["A"], sigma=d["sigma"], dt=0.005, max_steps=2000, threshold=1e3)
+            for d in draws]
+    cache = os.environ.get("KG_TUNE_CACHE",
+                           os.path.join(ROOT, "paper_1501_04552_amd", "tune_cache.json"))
+    res, secs = kg.kg_batch_run(runs, tune=True, tune_cache=cache)
+    steps = sum(r["steps_done"] for r in res)
+    sweep_bytes = sum(11 * r["n"] ** 2 * (r["n"] // 2 + 1) * 16 * o["steps_done"]
+                      for r, o in zip(runs, res))
+    # sequential reference: the same runs one by one through kg_step (sample)
+    sample = runs[:args.sweep_seq_sample]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    seq_blown = []
+    for r in sample:
+        with kg.Solver(r["n"], r["dt"], blowup_threshold=r["threshold"]) as s:
+            s.set_state(torch.from_numpy(ki.gaussian(r["n"], r["A"], r["sigma"])).cuda())
+            st, done = s.step(r["max_steps"])
+            seq_blown.append(s.stats()[1])
+    torch.cuda.synchronize()
+    seq_secs = time.perf_counter() - t0
+    agree = sum(int(b == o["blew_up"]) for b, o in zip(seq_blown, res))
+    return {"workload": f"{len(runs)} runs, seed 0, n in {{48,64,96,128}}, A~U[0.5,4], "
+                        "sigma~U[0.5,2], dt=0.005, <=2000 steps, blow-up at max|u|>1e3, FP64",
+            "seconds": secs, "runs_per_hour": len(runs) / secs * 3600.0,
+            "run_steps_per_s": steps / secs, "blown_fraction": float(np.mean([o["blew_up"] for o in res])),
+            "model_GBs": sweep_bytes / secs / 1e9,
+            "sequential_kg_step": {"runs": len(sample), "seconds_incl_setup": seq_secs,
+                                   "runs_per_hour": len(sample) / seq_secs * 3600.0,
+                                   "labels_agree": agree}}
 
 
 def traffic_from_profiles(n):
@@ -149,13 +189,13 @@ def main():
     del src, dst
 
     steps_per_s = args.steps / elapsed
-    sweep = n * n * (n // 2 + 1) * 16
-    step_bytes = 11 * sweep
+    sweep_b = n * n * (n // 2 + 1) * 16  # one sweep of the FP64 half spectrum
+    step_bytes = 11 * sweep_b
     t32 = r32["elapsed"] / args.steps
     fp32 = {"steps_per_s": 1.0 / t32, "ms_per_step": 1e3 * t32,
             "speedup_vs_fp64": (1.0 / t32) / steps_per_s,
-            "step_model_GBs": 12 * sweep / 2 / t32 / 1e9,
-            "step_hbm_frac": 12 * sweep / 2 / t32 / 1e9 / HBM_PEAK_GBS,
+            "step_model_GBs": 12 * sweep_b / 2 / t32 / 1e9,
+            "step_hbm_frac": 12 * sweep_b / 2 / t32 / 1e9 / HBM_PEAK_GBS,
             "kernels_ms": dict(zip(kg.KERNELS, r32["ms"])),
             "energy_drift": r32["drift"],
             "precision_study": {"workload": f"{n}^3 A=1.5 sigma=1 dt={dt} 200 steps",
@@ -189,6 +229,8 @@ def main():
         "energy_drift": drift,
         "fp32": fp32,
     }
+    if not args.no_sweep:
+        line["sweep"] = sweep(args, kg, ki, torch)
     if not args.no_cpu_baseline and n <= 512:
         line["cpu_baseline"] = cpu_baseline(u0, dt)
     print(json.dumps(line), flush=True)

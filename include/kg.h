@@ -163,6 +163,58 @@ kg_status kg_save_state(kg_plan_t *plan, void *host_buf, size_t bytes);
 kg_status kg_load_state(kg_plan_t *plan, const void *host_buf, size_t bytes);
 
 /* ------------------------------------------------------------------------ */
+/* Batched parametric sweep                                                  */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * One run of a sweep: Gaussian initial data u(0) = A exp(-(x^2/sx^2 +
+ * y^2/sy^2 + z^2/sz^2)), u_t(0) = 0, on the periodic box of kg_batch_opts.L,
+ * stepped with eq. (2) in FP64 for max_steps steps or until max|u^n| exceeds
+ * threshold (or is non-finite).  Parametric blow-up studies without symmetry
+ * assumptions are the paper's motivation (Sec. 1).
+ */
+typedef struct {
+    int n;            /* grid points per axis: 32, 48, 64, 96 or 128 */
+    double A, sx, sy, sz;
+    double dt;        /* > 0 */
+    int max_steps;    /* >= 0 */
+    double threshold; /* <= 0: no blow-up test */
+} kg_run_desc;
+
+typedef struct {
+    int blew_up;      /* 1 if a level n <= max_steps blew up */
+    int steps_done;   /* the blown level n, else max_steps */
+    double t_blowup;  /* n * dt for a blow-up, else -1 */
+    double E0;        /* E^{-1/2} of the initial pair (see kg_energy) */
+    double E_final;   /* E^{n-1/2} at n = max_steps (NaN after a blow-up) */
+    double max_abs_u; /* max of max|u^m| over the levels m computed (NaN if non-finite) */
+} kg_run_result;
+
+typedef struct {
+    double L;               /* box length per axis; <= 0 selects 8*pi */
+    int graph_steps;        /* steps per captured graph; <= 0 selects 10 */
+    int tune;               /* nonzero: tune the tile width of sizes missing from the cache */
+    const char *tune_cache; /* tile-width cache (JSON); NULL: $KG_TUNE_CACHE, else none */
+    double *seconds;        /* if not NULL: wall time of the stepping (set-up excluded) */
+} kg_batch_opts;
+
+/*
+ * Run every descriptor in one batch on the GPU of the current device: each
+ * pass of a step is one persistent launch over the tiles of all active runs
+ * of all sizes, steps are replayed from captured hipGraphs, and runs retire
+ * independently on blow-up or at max_steps.  runs and out are host arrays of
+ * nruns entries owned by the caller; opts may be NULL.  The library
+ * allocates and frees its own device memory.  A run that blows up is a
+ * result, not an error.  Errors: KG_E_INVALID (bad descriptor),
+ * KG_E_UNSUPPORTED_SIZE, KG_E_NOMEM, KG_E_HIP.
+ */
+kg_status kg_batch_run(const kg_run_desc *runs, int nruns, kg_run_result *out,
+                       const kg_batch_opts *opts, void *hip_stream);
+
+/* Message of the last kg_batch_run failure on this thread (static storage). */
+const char *kg_batch_last_error(void);
+
+/* ------------------------------------------------------------------------ */
 /* Test and measurement hooks (not needed to run the solver).               */
 /* ------------------------------------------------------------------------ */
 

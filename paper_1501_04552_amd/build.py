@@ -6,14 +6,16 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libkg.so")
-SOURCES = [os.path.join(CSRC, "kg_api.hip")]
-HEADERS = [os.path.join(CSRC, f) for f in ("kg_fft.hpp", "kg_kernels.hpp")] + \
+SOURCES = [os.path.join(CSRC, f) for f in ("kg_api.hip", "kg_ops_f64.hip", "kg_ops_f32.hip",
+                                            "kg_batch.hip")]
+HEADERS = [os.path.join(CSRC, f) for f in ("kg_fft.hpp", "kg_kernels.hpp", "kg_plan.hpp",
+                                            "kg_batch.hpp")] + \
     [os.path.join(ROOT, "include", "kg.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # packed fp32 instructions are kept out of all device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-result",
@@ -21,12 +23,26 @@ FLAGS = [
 
 
 def build(verbose=False):
-    """Compile every source into libkg.so (always recompiles)."""
+    """Compile every source (in parallel) and link libkg.so; always recompiles."""
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    procs = []
+    objs = []
+    for src in SOURCES:
+        obj = os.path.join(objdir, os.path.basename(src) + ".o")
+        objs.append(obj)
+        cmd = [HIPCC] + FLAGS + ["-I", os.path.join(ROOT, "include"), "-c", src, "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((cmd, subprocess.Popen(cmd)))
+    for cmd, pr in procs:
+        if pr.wait() != 0:
+            raise subprocess.CalledProcessError(pr.returncode, cmd)
     tmp = LIB + ".tmp"
-    cmd = [HIPCC] + FLAGS + ["-I", os.path.join(ROOT, "include")] + SOURCES + ["-o", tmp]
+    link = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC"] + objs + ["-o", tmp]
     if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
+        print(" ".join(link), flush=True)
+    subprocess.run(link, check=True)
     os.replace(tmp, LIB)
     return LIB
 

@@ -14,8 +14,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/kg.h"
-#include "kg_kernels.hpp"
+#include "kg_plan.hpp"
 
 using namespace kg;
 
@@ -23,152 +22,6 @@ namespace {
 
 constexpr size_t ALIGN = 256;
 size_t up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
-
-using Plan = kg_plan_s;
-
-// Kernel launchers for one (precision, grid size, tile width).
-struct Ops {
-    virtual ~Ops() = default;
-    virtual void x(Plan &pl, int mode, const double *rin, double *rout, double chi,
-                   const double *rin2 = nullptr) = 0;
-    virtual void y(Plan &pl, int dir, bool check_flag) = 0;
-    virtual void z(Plan &pl, int mode, void *Sp, void *Sc, double scale, int has_vel,
-                   const void *Ssub = nullptr) = 0;
-    virtual void pair_energy(Plan &pl, const void *S0, const void *S1) = 0;
-    virtual void state_to_spec(Plan &pl, const void *S, const void *Ssub, double *out) = 0;
-    virtual void q_to_spec(Plan &pl, double *out) = 0;
-    virtual void spec_to_q(Plan &pl, const double *in) = 0;
-    virtual long x_blocks() const = 0;
-    virtual long z_blocks(int ntx) const = 0;
-};
-
-}  // namespace
-
-struct kg_plan_s {
-    kg_params p{};
-    int n = 0, H = 0, W = 0, ntx = 0, P = 0;
-    double L = 0, h3 = 0, ks2 = 0, invM = 0, escale = 0, chi = 1;
-    size_t esz = 16;
-    hipStream_t stream = nullptr;
-    void *ws = nullptr;
-    bool own_ws = false;
-    size_t ws_bytes = 0;
-    char *Q = nullptr, *S[2] = {nullptr, nullptr}, *tw = nullptr;
-    double *partA = nullptr, *partC = nullptr, *sub = nullptr;
-    Rec *rec = nullptr;
-    Ctl *ctl = nullptr;
-    long nA = 0, nC = 0;
-    size_t q_bytes = 0, s_bytes = 0;
-    long steps = 0;  // steps launched since the state was set
-    bool ready = false;
-    std::unique_ptr<Ops> ops;
-    std::vector<hipEvent_t> tev;  // events of KG_STEP_TIMED calls
-    hipStream_t cap = nullptr;    // private stream used only to capture graphs
-    hipGraphExec_t gexec[2] = {nullptr, nullptr};  // GRAPH_STEPS steps from parity 0 / 1
-    double kt_ms[5] = {0, 0, 0, 0, 0};
-    int kt_steps = 0;
-    std::string err;
-};
-
-namespace {
-
-constexpr int PAIR_BLOCKS = 1024;
-
-template <typename T, int N, int W>
-struct OpsImpl final : Ops {
-    using YC = YZCfg<N, W>;
-    static long yz_grid(int ntx) { return (long)ntx * ((N + YC::B - 1) / YC::B); }
-
-    long x_blocks() const override { return XCfg<N>::blocks(); }
-    long z_blocks(int ntx) const override { return yz_grid(ntx); }
-
-    void x(Plan &pl, int mode, const double *rin, double *rout, double chi,
-           const double *rin2) override
-    {
-        XArgs<T> a;
-        a.Q = (cx<T> *)pl.Q;
-        a.tw = (const cx<T> *)pl.tw;
-        a.rin = rin;
-        a.rin2 = rin2;
-        a.rout = rout;
-        a.part = pl.partA;
-        a.ctl = pl.ctl;
-        a.P = pl.P;
-        a.chi = (T)chi;
-        dim3 g((unsigned)XCfg<N>::blocks()), b(256);
-        switch (mode) {
-        case X_STEP: hipLaunchKernelGGL((k_xpass<T, N, X_STEP>), g, b, 0, pl.stream, a); break;
-        case X_REDUCE: hipLaunchKernelGGL((k_xpass<T, N, X_REDUCE>), g, b, 0, pl.stream, a); break;
-        case X_R2C: hipLaunchKernelGGL((k_xpass<T, N, X_R2C>), g, b, 0, pl.stream, a); break;
-        case X_C2R: hipLaunchKernelGGL((k_xpass<T, N, X_C2R>), g, b, 0, pl.stream, a); break;
-        }
-    }
-    void y(Plan &pl, int dir, bool check_flag) override
-    {
-        YArgs<T> a;
-        a.Q = (cx<T> *)pl.Q;
-        a.tw = (const cx<T> *)pl.tw;
-        a.ctl = check_flag ? pl.ctl : nullptr;
-        a.P = pl.P;
-        a.H = pl.H;
-        a.ntx = pl.ntx;
-        dim3 g((unsigned)yz_grid(pl.ntx)), b(YC::NT);
-        if (dir < 0)
-            hipLaunchKernelGGL((k_ypass<T, N, W, -1>), g, b, 0, pl.stream, a);
-        else
-            hipLaunchKernelGGL((k_ypass<T, N, W, 1>), g, b, 0, pl.stream, a);
-    }
-    void z(Plan &pl, int mode, void *Sp, void *Sc, double scale, int has_vel,
-           const void *Ssub) override
-    {
-        ZArgs<T> a;
-        a.Q = (cx<T> *)pl.Q;
-        a.tw = (const cx<T> *)pl.tw;
-        a.Sp = (cx<T> *)Sp;
-        a.Sc = (cx<T> *)Sc;
-        a.Ssub = (const cx<T> *)Ssub;
-        a.part = pl.partC;
-        a.ctl = pl.ctl;
-        a.P = pl.P;
-        a.H = pl.H;
-        a.ntx = pl.ntx;
-        a.ks2 = pl.ks2;
-        a.dt = pl.p.dt;
-        a.chi = pl.chi;
-        a.scale = scale;
-        a.has_vel = has_vel;
-        dim3 g((unsigned)yz_grid(pl.ntx)), b(YC::NT);
-        switch (mode) {
-        case Z_STEP: hipLaunchKernelGGL((k_zpass<T, N, W, Z_STEP>), g, b, 0, pl.stream, a); break;
-        case Z_FWD_STATE: hipLaunchKernelGGL((k_zpass<T, N, W, Z_FWD_STATE>), g, b, 0, pl.stream, a); break;
-        case Z_FWD_Q: hipLaunchKernelGGL((k_zpass<T, N, W, Z_FWD_Q>), g, b, 0, pl.stream, a); break;
-        case Z_INV_STATE: hipLaunchKernelGGL((k_zpass<T, N, W, Z_INV_STATE>), g, b, 0, pl.stream, a); break;
-        case Z_INV_Q: hipLaunchKernelGGL((k_zpass<T, N, W, Z_INV_Q>), g, b, 0, pl.stream, a); break;
-        case Z_START: hipLaunchKernelGGL((k_zpass<T, N, W, Z_START>), g, b, 0, pl.stream, a); break;
-        }
-    }
-    void pair_energy(Plan &pl, const void *S0, const void *S1) override
-    {
-        hipLaunchKernelGGL((k_pair_energy<T, N, W>), dim3(PAIR_BLOCKS), dim3(256), 0, pl.stream,
-                           (const cx<T> *)S0, (const cx<T> *)S1, pl.partC, pl.H, pl.ntx, pl.ks2,
-                           pl.p.dt);
-    }
-    void state_to_spec(Plan &pl, const void *S, const void *Ssub, double *out) override
-    {
-        hipLaunchKernelGGL((k_state_to_spec<T, N, W>), dim3(2048), dim3(256), 0, pl.stream,
-                           (const cx<T> *)S, (const cx<T> *)Ssub, out, pl.H, pl.ntx);
-    }
-    void q_to_spec(Plan &pl, double *out) override
-    {
-        hipLaunchKernelGGL((k_q_to_spec<T>), dim3(2048), dim3(256), 0, pl.stream,
-                           (const cx<T> *)pl.Q, out, pl.P, pl.H, (long)N * N);
-    }
-    void spec_to_q(Plan &pl, const double *in) override
-    {
-        hipLaunchKernelGGL((k_spec_to_q<T>), dim3(2048), dim3(256), 0, pl.stream, in,
-                           (cx<T> *)pl.Q, pl.P, pl.H, (long)N * N);
-    }
-};
 
 // Tile width of the y and z passes: W complex columns give 16*W-byte (FP64)
 // or 8*W-byte (FP32) row segments per wavefront access.  Whole 128-byte
@@ -186,30 +39,10 @@ int tile_width(int precision)
     return def;
 }
 
-template <typename T, int W>
-std::unique_ptr<Ops> make_ops_w(int n)
-{
-    switch (n) {
-    case 24: return std::make_unique<OpsImpl<T, 24, W>>();
-    case 48: return std::make_unique<OpsImpl<T, 48, W>>();
-    case 96: return std::make_unique<OpsImpl<T, 96, W>>();
-    case 192: return std::make_unique<OpsImpl<T, 192, W>>();
-    case 384: return std::make_unique<OpsImpl<T, 384, W>>();
-    case 8: return std::make_unique<OpsImpl<T, 8, W>>();
-    case 16: return std::make_unique<OpsImpl<T, 16, W>>();
-    case 32: return std::make_unique<OpsImpl<T, 32, W>>();
-    case 64: return std::make_unique<OpsImpl<T, 64, W>>();
-    case 128: return std::make_unique<OpsImpl<T, 128, W>>();
-    case 256: return std::make_unique<OpsImpl<T, 256, W>>();
-    case 512: return std::make_unique<OpsImpl<T, 512, W>>();
-    default: return nullptr;
-    }
-}
-
 std::unique_ptr<Ops> make_ops(int n, int precision, int W)
 {
-    if (precision == KG_FP64) return W == 4 ? make_ops_w<double, 4>(n) : make_ops_w<double, 8>(n);
-    if (precision == KG_FP32) return W == 8 ? make_ops_w<float, 8>(n) : make_ops_w<float, 16>(n);
+    if (precision == KG_FP64) return make_ops_f64(n, W);
+    if (precision == KG_FP32) return make_ops_f32(n, W);
     return nullptr;
 }
 

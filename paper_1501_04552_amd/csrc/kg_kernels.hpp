@@ -92,7 +92,7 @@ __device__ __forceinline__ void block_max_sum(double mx, double sm, double *out)
 // x pass
 // ---------------------------------------------------------------------------
 
-enum XMode { X_STEP = 0, X_REDUCE = 1, X_R2C = 2, X_C2R = 3 };
+enum XMode { X_STEP = 0, X_REDUCE = 1, X_R2C = 2, X_C2R = 3, X_GAUSS = 4 };
 
 template <typename T>
 struct XArgs {
@@ -104,7 +104,10 @@ struct XArgs {
     double *part;         // X_STEP / X_REDUCE: (max|u|, sum u^4) per workgroup
     const Ctl *ctl;
     int P;                // row pitch of Q
-    T chi;                // cubic coefficient (X_STEP; X_R2C: 1 cubes the input)
+    T chi;                // cubic coefficient (X_STEP; X_R2C / X_GAUSS: 1 cubes the input)
+    // X_GAUSS: the input is A exp(-(x^2/sx^2 + y^2/sy^2 + z^2/sz^2)) sampled at
+    // x_j = -L/2 + j L / N (same for y, z), computed in place of rin
+    double gA, gsx, gsy, gsz, gL;
 };
 
 // Two real x-lines u1, u2 are transformed together as one complex line
@@ -122,25 +125,42 @@ struct XCfg {
     static constexpr long blocks() { return ((long)N * N / 2 + PPB - 1) / PPB; }
 };
 
+// One workgroup's share of the x pass: line pairs blk*PPB .. blk*PPB+PPB-1.
+// rows: LDS of XCfg<N>::PPB * RS elements; part: the workgroup's partial slot.
 template <typename T, int N, int MODE>
-__global__ __launch_bounds__(256) void k_xpass(XArgs<T> a)
+__device__ __forceinline__ void xbody(const XArgs<T> &a, long blk, cx<T> *rows, double *part)
 {
     using C = XCfg<N>;
     constexpr int E = Radix<N>::E, TPL = C::TPL, PPB = C::PPB, RS = C::RS, NH = N / 2;
     // a pair's threads never span two waves, so its stages sync per wave
     constexpr int XSY = (64 % TPL == 0) ? SYNC_WAVE : SYNC_BLOCK;
-    __shared__ cx<T> rows[PPB * RS];
-    if constexpr (MODE == X_STEP || MODE == X_REDUCE) {
-        if (a.ctl->flag) return;
-    }
     const int t = threadIdx.x % TPL, l = threadIdx.x / TPL;
-    const long pr = (long)blockIdx.x * PPB + l;
+    const long pr = blk * PPB + l;
     const bool act = pr < (long)N * N / 2;
     cx<T> *r = rows + l * RS;
     cx<T> v[E];
     double mx = 0.0, s4 = 0.0;
 
-    if constexpr (MODE == X_R2C) {
+    if constexpr (MODE == X_GAUSS) {
+        const long l1 = 2 * pr;  // first line of the pair: (z, y) = (l1 / N, l1 % N)
+        const double h = a.gL / N;
+        const double y1 = -0.5 * a.gL + (double)(l1 % N) * h, z1 = -0.5 * a.gL + (double)(l1 / N) * h;
+        const double y2 = -0.5 * a.gL + (double)((l1 + 1) % N) * h;
+        const double z2 = -0.5 * a.gL + (double)((l1 + 1) / N) * h;
+        const double ry1 = y1 * y1 / (a.gsy * a.gsy) + z1 * z1 / (a.gsz * a.gsz);
+        const double ry2 = y2 * y2 / (a.gsy * a.gsy) + z2 * z2 / (a.gsz * a.gsz);
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+            const int m = t + j * TPL;
+            const double x = -0.5 * a.gL + (double)m * h, rx = x * x / (a.gsx * a.gsx);
+            double d1 = act ? a.gA * exp(-(rx + ry1)) : 0.0, d2 = act ? a.gA * exp(-(rx + ry2)) : 0.0;
+            if (a.chi != (T)0) {
+                d1 = d1 * d1 * d1;
+                d2 = d2 * d2 * d2;
+            }
+            v[j] = mk((T)d1, (T)d2);
+        }
+    } else if constexpr (MODE == X_R2C) {
         const double *s1 = a.rin + (2 * pr) * N, *s2 = s1 + N;
 #pragma unroll
         for (int j = 0; j < E; ++j) {
@@ -198,7 +218,7 @@ __global__ __launch_bounds__(256) void k_xpass(XArgs<T> a)
             }
         }
         if constexpr (MODE == X_REDUCE) {
-            block_max_sum<256>(mx, s4, a.part + 2 * blockIdx.x);
+            block_max_sum<256>(mx, s4, part);
             return;
         }
 #pragma unroll
@@ -230,7 +250,17 @@ __global__ __launch_bounds__(256) void k_xpass(XArgs<T> a)
             }
         }
     }
-    if constexpr (MODE == X_STEP) block_max_sum<256>(mx, s4, a.part + 2 * blockIdx.x);
+    if constexpr (MODE == X_STEP) block_max_sum<256>(mx, s4, part);
+}
+
+template <typename T, int N, int MODE>
+__global__ __launch_bounds__(256) void k_xpass(XArgs<T> a)
+{
+    __shared__ cx<T> rows[XCfg<N>::PPB * XCfg<N>::RS];
+    if constexpr (MODE == X_STEP || MODE == X_REDUCE) {
+        if (a.ctl->flag) return;
+    }
+    xbody<T, N, MODE>(a, blockIdx.x, rows, a.part + 2 * blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -253,15 +283,14 @@ struct YArgs {
     int P, H, ntx;
 };
 
+// One workgroup's tile of the y pass: columns tile*W.. of B consecutive z planes.
 template <typename T, int N, int W, int DIR>
-__global__ __launch_bounds__((YZCfg<N, W>::NT)) void k_ypass(YArgs<T> a)
+__device__ __forceinline__ void ybody(const YArgs<T> &a, long blk, cx<T> *lds)
 {
     using C = YZCfg<N, W>;
     constexpr int E = Radix<N>::E, TPL = C::TPL, B = C::B;
-    __shared__ cx<T> lds[W * B * lslots<N>()];
-    if (a.ctl && a.ctl->flag) return;
     const int c = threadIdx.x % W, t = (threadIdx.x / W) % TPL, b = threadIdx.x / (W * TPL);
-    const int tile = blockIdx.x % a.ntx, z = (blockIdx.x / a.ntx) * B + b;
+    const int tile = (int)(blk % a.ntx), z = (int)(blk / a.ntx) * B + b;
     const int kx = tile * W + c;
     const bool act = kx < a.H && z < N;
     cx<T> *g = a.Q + ((long)z * N) * a.P + kx;
@@ -275,6 +304,15 @@ __global__ __launch_bounds__((YZCfg<N, W>::NT)) void k_ypass(YArgs<T> a)
     }
 }
 
+template <typename T, int N, int W, int DIR>
+__global__ __launch_bounds__((YZCfg<N, W>::NT)) void k_ypass(YArgs<T> a)
+{
+    using C = YZCfg<N, W>;
+    __shared__ cx<T> lds[W * C::B * lslots<N>()];
+    if (a.ctl && a.ctl->flag) return;
+    ybody<T, N, W, DIR>(a, blockIdx.x, lds);
+}
+
 // ---------------------------------------------------------------------------
 // z pass: c2c along z, with the eq. (2) update on the hot path
 // ---------------------------------------------------------------------------
@@ -285,7 +323,8 @@ enum ZMode {
     Z_FWD_Q = 2,      // forward z in place
     Z_INV_STATE = 3,  // state buffer * scale -> inverse z -> Q
     Z_INV_Q = 4,      // inverse z in place, times scale
-    Z_START = 5       // symmetric start: Sp = (alpha/2) Sc - dt Fz(Q) + (beta/2) chi Sp
+    Z_START = 5,      // symmetric start: Sp = (alpha/2) Sc - dt Fz(Q) + (beta/2) chi Sp
+    Z_PAIR = 6        // energy partial of the stored pair (Sp = v^{-1}, Sc = v^0), no transform
 };
 
 // Time levels.  FP64 keeps two levels, v^n and v^{n-1} (Sp holds v^{n-1} and
@@ -325,17 +364,14 @@ __device__ __forceinline__ void coeffs(int mx, int my, int mz, double ks2, doubl
     be = dt * dt * inv;
 }
 
+// One workgroup's tile of the z pass: columns tile*W.. of B consecutive ky.
 template <typename T, int N, int W, int MODE>
-__global__ __launch_bounds__((YZCfg<N, W>::NT)) void k_zpass(ZArgs<T> a)
+__device__ __forceinline__ void zbody(const ZArgs<T> &a, long blk, cx<T> *lds, double *part)
 {
     using C = YZCfg<N, W>;
     constexpr int E = Radix<N>::E, TPL = C::TPL, B = C::B, NT = C::NT;
-    __shared__ cx<T> lds[W * B * lslots<N>()];
-    if constexpr (MODE == Z_STEP) {
-        if (a.ctl->flag) return;
-    }
     const int c = threadIdx.x % W, t = (threadIdx.x / W) % TPL, b = threadIdx.x / (W * TPL);
-    const int tile = blockIdx.x % a.ntx, ky = (blockIdx.x / a.ntx) * B + b;
+    const int tile = (int)(blk % a.ntx), ky = (int)(blk / a.ntx) * B + b;
     const int kx = tile * W + c;
     const bool act = kx < a.H && ky < N;
     const long zs = (long)N * a.P;
@@ -345,6 +381,37 @@ __global__ __launch_bounds__((YZCfg<N, W>::NT)) void k_zpass(ZArgs<T> a)
     const cx<T> zero = mk<T>(0, 0);
     cx<T> v[E];
 
+    if constexpr (MODE == Z_PAIR) {
+        double esum = 0.0;
+        if (act) {
+            const int my = ky <= N / 2 ? ky : ky - N;
+            const double wgt = (kx == 0 || kx == N / 2) ? 1.0 : 2.0;
+            const double idt2 = 1.0 / (a.dt * a.dt);
+#pragma unroll
+            for (int j = 0; j < E; ++j) {
+                const int kz = t + j * TPL, mz = kz <= N / 2 ? kz : kz - N;
+                double al, be, w2;
+                coeffs(kx, my, mz, a.ks2, a.dt, al, be, w2);
+                const long si = sbase + (long)kz * W;
+                const cx<T> a0 = a.Sp[si], a1 = a.Sc[si];
+                double dr, di, sr, sim;
+                if constexpr (increment_form<T>()) {  // Sc = v^0, Sp = Delta^0
+                    dr = (double)a0.re;
+                    di = (double)a0.im;
+                    sr = 2.0 * (double)a1.re - dr;
+                    sim = 2.0 * (double)a1.im - di;
+                } else {
+                    dr = (double)a1.re - (double)a0.re;
+                    di = (double)a1.im - (double)a0.im;
+                    sr = (double)a1.re + (double)a0.re;
+                    sim = (double)a1.im + (double)a0.im;
+                }
+                esum += wgt * ((dr * dr + di * di) * idt2 + 0.25 * w2 * (sr * sr + sim * sim));
+            }
+        }
+        block_max_sum<NT>(0.0, esum, part);
+        return;
+    }
     if constexpr (MODE == Z_STEP || MODE == Z_FWD_STATE || MODE == Z_FWD_Q || MODE == Z_START) {
         if (MODE != Z_START || a.has_vel) {
 #pragma unroll
@@ -458,7 +525,18 @@ __global__ __launch_bounds__((YZCfg<N, W>::NT)) void k_zpass(ZArgs<T> a)
 #pragma unroll
         for (int j = 0; j < E; ++j) st_nt(g + (t + j * TPL) * zs, v[j]);
     }
-    if constexpr (MODE == Z_STEP) block_max_sum<NT>(0.0, esum, a.part + 2 * blockIdx.x);
+    if constexpr (MODE == Z_STEP) block_max_sum<NT>(0.0, esum, part);
+}
+
+template <typename T, int N, int W, int MODE>
+__global__ __launch_bounds__((YZCfg<N, W>::NT)) void k_zpass(ZArgs<T> a)
+{
+    using C = YZCfg<N, W>;
+    __shared__ cx<T> lds[W * C::B * lslots<N>()];
+    if constexpr (MODE == Z_STEP) {
+        if (a.ctl->flag) return;
+    }
+    zbody<T, N, W, MODE>(a, blockIdx.x, lds, a.part + 2 * blockIdx.x);
 }
 
 // Linear energy partials of a pair of levels stored in the state layout:
@@ -555,7 +633,7 @@ __global__ __launch_bounds__(256) void k_spec_to_q(const double *in, cx<T> *Q, i
 // the result is bitwise reproducible.
 constexpr int RSUB = 128;
 
-__global__ __launch_bounds__(256) void k_reduce_partials(const double *partA, int nA,
+static __global__ __launch_bounds__(256) void k_reduce_partials(const double *partA, int nA,
                                                          const double *partC, int nC, double *sub,
                                                          const Ctl *ctl, int check_flag)
 {
@@ -592,7 +670,7 @@ __global__ __launch_bounds__(256) void k_reduce_partials(const double *partA, in
 //   mode 0 (step):   rec[step] = {elin, q4, maxu}; blow-up test; step counter.
 //   mode 1 (reduce): rec[step].q4/maxu from the x-pass partials only.
 //   mode 2 (init):   ctl->elin_m, q4_m, maxu_m.
-__global__ __launch_bounds__(RSUB) void k_finalize(const double *sub, Rec *rec, Ctl *ctl,
+static __global__ __launch_bounds__(RSUB) void k_finalize(const double *sub, Rec *rec, Ctl *ctl,
                                                    double thr, double escale, double h3, int mode)
 {
     if (mode != 2 && ctl->flag) return;
@@ -634,7 +712,7 @@ __global__ __launch_bounds__(RSUB) void k_finalize(const double *sub, Rec *rec, 
 
 // Plain copy (bandwidth ceiling and counter calibration): every byte read and
 // written once, four 16-byte values in flight per thread, streaming hints.
-__global__ __launch_bounds__(256) void k_copy(uint4 *dst, const uint4 *src, long n16)
+static __global__ __launch_bounds__(256) void k_copy(uint4 *dst, const uint4 *src, long n16)
 {
     typedef unsigned v4u __attribute__((ext_vector_type(4)));
     const long stride = (long)gridDim.x * 256 * 4;

@@ -1,0 +1,168 @@
+// kg_plan.hpp -- host-side plan object and the kernel launchers per
+// (precision, grid size, tile width), shared by the translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/kg.h"
+#include "kg_kernels.hpp"
+
+namespace kg {
+
+struct Ops;
+
+}  // namespace kg
+
+struct kg_plan_s {
+    kg_params p{};
+    int n = 0, H = 0, W = 0, ntx = 0, P = 0;
+    double L = 0, h3 = 0, ks2 = 0, invM = 0, escale = 0, chi = 1;
+    size_t esz = 16;
+    hipStream_t stream = nullptr;
+    void *ws = nullptr;
+    bool own_ws = false;
+    size_t ws_bytes = 0;
+    char *Q = nullptr, *S[2] = {nullptr, nullptr}, *tw = nullptr;
+    double *partA = nullptr, *partC = nullptr, *sub = nullptr;
+    kg::Rec *rec = nullptr;
+    kg::Ctl *ctl = nullptr;
+    long nA = 0, nC = 0;
+    size_t q_bytes = 0, s_bytes = 0;
+    long steps = 0;  // steps launched since the state was set
+    bool ready = false;
+    std::unique_ptr<kg::Ops> ops;
+    std::vector<hipEvent_t> tev;  // events of KG_STEP_TIMED calls
+    hipStream_t cap = nullptr;    // private stream used only to capture graphs
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};  // GRAPH_STEPS steps from parity 0 / 1
+    double kt_ms[5] = {0, 0, 0, 0, 0};
+    int kt_steps = 0;
+    std::string err;
+};
+
+namespace kg {
+
+using Plan = kg_plan_s;
+
+constexpr int PAIR_BLOCKS = 1024;
+
+// Kernel launchers for one (precision, grid size, tile width).
+struct Ops {
+    virtual ~Ops() = default;
+    virtual void x(Plan &pl, int mode, const double *rin, double *rout, double chi,
+                   const double *rin2 = nullptr) = 0;
+    virtual void y(Plan &pl, int dir, bool check_flag) = 0;
+    virtual void z(Plan &pl, int mode, void *Sp, void *Sc, double scale, int has_vel,
+                   const void *Ssub = nullptr) = 0;
+    virtual void pair_energy(Plan &pl, const void *S0, const void *S1) = 0;
+    virtual void state_to_spec(Plan &pl, const void *S, const void *Ssub, double *out) = 0;
+    virtual void q_to_spec(Plan &pl, double *out) = 0;
+    virtual void spec_to_q(Plan &pl, const double *in) = 0;
+    virtual long x_blocks() const = 0;
+    virtual long z_blocks(int ntx) const = 0;
+};
+
+// Launchers of one precision (defined in kg_ops_f64.hip / kg_ops_f32.hip).
+std::unique_ptr<Ops> make_ops_f64(int n, int W);
+std::unique_ptr<Ops> make_ops_f32(int n, int W);
+
+template <typename T, int N, int W>
+struct OpsImpl final : Ops {
+    using YC = YZCfg<N, W>;
+    static long yz_grid(int ntx) { return (long)ntx * ((N + YC::B - 1) / YC::B); }
+
+    long x_blocks() const override { return XCfg<N>::blocks(); }
+    long z_blocks(int ntx) const override { return yz_grid(ntx); }
+
+    void x(Plan &pl, int mode, const double *rin, double *rout, double chi,
+           const double *rin2) override
+    {
+        XArgs<T> a{};
+        a.Q = (cx<T> *)pl.Q;
+        a.tw = (const cx<T> *)pl.tw;
+        a.rin = rin;
+        a.rin2 = rin2;
+        a.rout = rout;
+        a.part = pl.partA;
+        a.ctl = pl.ctl;
+        a.P = pl.P;
+        a.chi = (T)chi;
+        dim3 g((unsigned)XCfg<N>::blocks()), b(256);
+        switch (mode) {
+        case X_STEP: hipLaunchKernelGGL((k_xpass<T, N, X_STEP>), g, b, 0, pl.stream, a); break;
+        case X_REDUCE: hipLaunchKernelGGL((k_xpass<T, N, X_REDUCE>), g, b, 0, pl.stream, a); break;
+        case X_R2C: hipLaunchKernelGGL((k_xpass<T, N, X_R2C>), g, b, 0, pl.stream, a); break;
+        case X_C2R: hipLaunchKernelGGL((k_xpass<T, N, X_C2R>), g, b, 0, pl.stream, a); break;
+        }
+    }
+    void y(Plan &pl, int dir, bool check_flag) override
+    {
+        YArgs<T> a{};
+        a.Q = (cx<T> *)pl.Q;
+        a.tw = (const cx<T> *)pl.tw;
+        a.ctl = check_flag ? pl.ctl : nullptr;
+        a.P = pl.P;
+        a.H = pl.H;
+        a.ntx = pl.ntx;
+        dim3 g((unsigned)yz_grid(pl.ntx)), b(YC::NT);
+        if (dir < 0)
+            hipLaunchKernelGGL((k_ypass<T, N, W, -1>), g, b, 0, pl.stream, a);
+        else
+            hipLaunchKernelGGL((k_ypass<T, N, W, 1>), g, b, 0, pl.stream, a);
+    }
+    void z(Plan &pl, int mode, void *Sp, void *Sc, double scale, int has_vel,
+           const void *Ssub) override
+    {
+        ZArgs<T> a{};
+        a.Q = (cx<T> *)pl.Q;
+        a.tw = (const cx<T> *)pl.tw;
+        a.Sp = (cx<T> *)Sp;
+        a.Sc = (cx<T> *)Sc;
+        a.Ssub = (const cx<T> *)Ssub;
+        a.part = pl.partC;
+        a.ctl = pl.ctl;
+        a.P = pl.P;
+        a.H = pl.H;
+        a.ntx = pl.ntx;
+        a.ks2 = pl.ks2;
+        a.dt = pl.p.dt;
+        a.chi = pl.chi;
+        a.scale = scale;
+        a.has_vel = has_vel;
+        dim3 g((unsigned)yz_grid(pl.ntx)), b(YC::NT);
+        switch (mode) {
+        case Z_STEP: hipLaunchKernelGGL((k_zpass<T, N, W, Z_STEP>), g, b, 0, pl.stream, a); break;
+        case Z_FWD_STATE: hipLaunchKernelGGL((k_zpass<T, N, W, Z_FWD_STATE>), g, b, 0, pl.stream, a); break;
+        case Z_FWD_Q: hipLaunchKernelGGL((k_zpass<T, N, W, Z_FWD_Q>), g, b, 0, pl.stream, a); break;
+        case Z_INV_STATE: hipLaunchKernelGGL((k_zpass<T, N, W, Z_INV_STATE>), g, b, 0, pl.stream, a); break;
+        case Z_INV_Q: hipLaunchKernelGGL((k_zpass<T, N, W, Z_INV_Q>), g, b, 0, pl.stream, a); break;
+        case Z_START: hipLaunchKernelGGL((k_zpass<T, N, W, Z_START>), g, b, 0, pl.stream, a); break;
+        }
+    }
+    void pair_energy(Plan &pl, const void *S0, const void *S1) override
+    {
+        hipLaunchKernelGGL((k_pair_energy<T, N, W>), dim3(PAIR_BLOCKS), dim3(256), 0, pl.stream,
+                           (const cx<T> *)S0, (const cx<T> *)S1, pl.partC, pl.H, pl.ntx, pl.ks2,
+                           pl.p.dt);
+    }
+    void state_to_spec(Plan &pl, const void *S, const void *Ssub, double *out) override
+    {
+        hipLaunchKernelGGL((k_state_to_spec<T, N, W>), dim3(2048), dim3(256), 0, pl.stream,
+                           (const cx<T> *)S, (const cx<T> *)Ssub, out, pl.H, pl.ntx);
+    }
+    void q_to_spec(Plan &pl, double *out) override
+    {
+        hipLaunchKernelGGL((k_q_to_spec<T>), dim3(2048), dim3(256), 0, pl.stream,
+                           (const cx<T> *)pl.Q, out, pl.P, pl.H, (long)N * N);
+    }
+    void spec_to_q(Plan &pl, const double *in) override
+    {
+        hipLaunchKernelGGL((k_spec_to_q<T>), dim3(2048), dim3(256), 0, pl.stream, in,
+                           (cx<T> *)pl.Q, pl.P, pl.H, (long)N * N);
+    }
+};
+
+}  // namespace kg

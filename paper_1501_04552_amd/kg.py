@@ -34,6 +34,23 @@ class kg_params(ctypes.Structure):
                 ("blowup_threshold", ctypes.c_double)]
 
 
+class kg_run_desc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("A", ctypes.c_double), ("sx", ctypes.c_double),
+                ("sy", ctypes.c_double), ("sz", ctypes.c_double), ("dt", ctypes.c_double),
+                ("max_steps", ctypes.c_int), ("threshold", ctypes.c_double)]
+
+
+class kg_run_result(ctypes.Structure):
+    _fields_ = [("blew_up", ctypes.c_int), ("steps_done", ctypes.c_int),
+                ("t_blowup", ctypes.c_double), ("E0", ctypes.c_double),
+                ("E_final", ctypes.c_double), ("max_abs_u", ctypes.c_double)]
+
+
+class kg_batch_opts(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_double), ("graph_steps", ctypes.c_int), ("tune", ctypes.c_int),
+                ("tune_cache", ctypes.c_char_p), ("seconds", ctypes.POINTER(ctypes.c_double))]
+
+
 _vp = ctypes.c_void_p
 _dp = ctypes.POINTER(ctypes.c_double)
 _ip = ctypes.POINTER(ctypes.c_int)
@@ -65,6 +82,10 @@ _SIGS = {
                                      ctypes.POINTER(ctypes.c_float)]),
     "kg_kernel_bytes": (ctypes.c_double, [_vp, ctypes.c_int]),
     "kg_kernel_times": (ctypes.c_int, [_vp, _dp, _ip]),
+    "kg_batch_run": (ctypes.c_int, [ctypes.POINTER(kg_run_desc), ctypes.c_int,
+                                    ctypes.POINTER(kg_run_result), ctypes.POINTER(kg_batch_opts),
+                                    _vp]),
+    "kg_batch_last_error": (ctypes.c_char_p, []),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -233,3 +254,24 @@ def kg_kernel_times(plan):
 
 def kg_kernel_bytes(plan, kernel):
     return _lib.kg_kernel_bytes(plan, kernel)
+
+
+def kg_batch_run(runs, L=0.0, graph_steps=0, tune=False, tune_cache=None, stream=None):
+    """Run a sweep.  runs: sequence of dicts with n, A, sigma (sx, sy, sz), dt,
+    max_steps, threshold.  Returns (list of result dicts, stepping seconds)."""
+    nr = len(runs)
+    desc = (kg_run_desc * nr)()
+    for d, r in zip(desc, runs):
+        sx, sy, sz = r["sigma"]
+        d.n, d.A, d.sx, d.sy, d.sz = int(r["n"]), float(r["A"]), float(sx), float(sy), float(sz)
+        d.dt, d.max_steps, d.threshold = float(r["dt"]), int(r["max_steps"]), float(r["threshold"])
+    out = (kg_run_result * nr)()
+    secs = ctypes.c_double(0.0)
+    opts = kg_batch_opts(float(L), int(graph_steps), int(bool(tune)),
+                         tune_cache.encode() if tune_cache else None, ctypes.pointer(secs))
+    st = _lib.kg_batch_run(desc, nr, out, ctypes.byref(opts), stream)
+    if st != KG_OK:
+        raise KGError(st, _lib.kg_batch_last_error().decode())
+    res = [dict(blew_up=bool(o.blew_up), steps_done=o.steps_done, t_blowup=o.t_blowup, E0=o.E0,
+                E_final=o.E_final, max_abs_u=o.max_abs_u) for o in out]
+    return res, secs.value

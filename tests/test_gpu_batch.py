@@ -1,0 +1,115 @@
+"""Batched parametric sweep (kg_batch_run): every run of a mixed-size batch
+must reproduce the same run done alone through kg_step, and runs must not
+affect each other.
+
+Tolerances: a batched run and a single run use the same kernels and the same
+per-column FFT arithmetic; only the Gaussian sampling (the library's exp on
+the GPU versus numpy's on the host, 1 ulp apart) and the order of the energy
+partial sums differ, so energies agree to ~1e-13 relative; 1e-11 is used.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import kg_inputs as ki
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+RUNS = [
+    dict(n=32, A=0.8, sigma=(1.0, 1.2, 0.9), dt=0.01, max_steps=120, threshold=1e3),
+    dict(n=48, A=3.5, sigma=(1.0, 1.0, 1.0), dt=0.005, max_steps=400, threshold=1e3),
+    dict(n=64, A=1.5, sigma=(0.7, 1.4, 1.1), dt=0.005, max_steps=150, threshold=1e3),
+    dict(n=32, A=4.0, sigma=(1.6, 1.3, 1.8), dt=0.005, max_steps=300, threshold=1e3),
+    dict(n=48, A=0.6, sigma=(0.5, 0.6, 0.7), dt=0.005, max_steps=90, threshold=1e3),
+]
+
+
+def single(kg, r):
+    u0 = ki.gaussian(r["n"], r["A"], r["sigma"])
+    with kg.Solver(r["n"], r["dt"], blowup_threshold=r["threshold"]) as s:
+        s.set_state(u0)
+        E0, _ = s.energy()
+        st, done = s.step(r["max_steps"])
+        steps, blown, bstep = s.stats()
+        rec = s.records(0, bstep + 1 if blown else steps)
+        E = s.energy()[0] if not blown else float("nan")
+    return dict(blew_up=blown, steps_done=bstep if blown else steps, E0=E0, E_final=E,
+                max_abs_u=float(np.nanmax(rec[2])))
+
+
+def test_batch_matches_single_runs(kg):
+    res, secs = kg.kg_batch_run(RUNS)
+    assert secs > 0
+    assert any(r["blew_up"] for r in res) and not all(r["blew_up"] for r in res)
+    for r, b in zip(RUNS, res):
+        s = single(kg, r)
+        assert b["blew_up"] == s["blew_up"]
+        assert b["steps_done"] == s["steps_done"]
+        assert abs(b["E0"] - s["E0"]) <= 1e-11 * abs(s["E0"])
+        if s["blew_up"]:
+            assert abs(b["t_blowup"] - s["steps_done"] * r["dt"]) < 1e-12
+            assert np.isnan(b["E_final"])
+        else:
+            assert b["t_blowup"] == -1.0
+            assert abs(b["E_final"] - s["E_final"]) <= 1e-11 * abs(s["E_final"])
+        assert abs(b["max_abs_u"] - s["max_abs_u"]) <= 1e-11 * s["max_abs_u"]
+
+
+def test_batch_runs_are_independent(kg):
+    """A poisoned run (it blows up at level 0) leaves the others bitwise unchanged."""
+    base, _ = kg.kg_batch_run(RUNS)
+    poison = dict(n=64, A=5e3, sigma=(1.0, 1.0, 1.0), dt=0.005, max_steps=100, threshold=1e3)
+    mixed, _ = kg.kg_batch_run(RUNS[:2] + [poison] + RUNS[2:])
+    assert mixed[2]["blew_up"] and mixed[2]["steps_done"] == 0
+    for a, b in zip(base, mixed[:2] + mixed[3:]):
+        for k in ("blew_up", "steps_done", "t_blowup", "max_abs_u"):
+            assert a[k] == b[k]
+        assert a["E0"] == b["E0"]
+        assert (np.isnan(a["E_final"]) and np.isnan(b["E_final"])) or a["E_final"] == b["E_final"]
+
+
+def test_batch_oracle_parity(kg):
+    """Two 32^3 runs against the CPU oracle (blow-up step, E0, final energy)."""
+    runs = [dict(n=32, A=1.2, sigma=(0.9, 1.1, 1.3), dt=0.01, max_steps=60, threshold=1e3),
+            dict(n=32, A=4.0, sigma=(1.0, 1.2, 0.9), dt=0.01, max_steps=400, threshold=1e3)]
+    res, _ = kg.kg_batch_run(runs)
+    for r, b in zip(runs, res):
+        ref = oracle.run(ki.gaussian(32, r["A"], r["sigma"]), r["dt"], r["max_steps"],
+                         threshold=r["threshold"])
+        assert b["blew_up"] == (ref["blowup_step"] >= 0)
+        assert abs(b["E0"] - ref["energy"][0]) <= 1e-11 * abs(ref["energy"][0])
+        if b["blew_up"]:
+            assert b["steps_done"] == ref["blowup_step"]
+        else:
+            E = ref["energy"][r["max_steps"]]
+            assert abs(b["E_final"] - E) <= 1e-11 * abs(E)
+
+
+def test_batch_sweep_sizes_and_autotuner(kg, tmp_path):
+    """The sweep's grid sizes, with the tile-width autotuner writing its cache."""
+    runs = [dict(n=n, A=A, sigma=(1.0, 0.8, 1.2), dt=0.005, max_steps=40, threshold=1e3)
+            for n in ki.SWEEP_SIZES for A in (0.7, 3.0)]
+    cache = str(tmp_path / "tune.json")
+    res, _ = kg.kg_batch_run(runs, tune=True, tune_cache=cache)
+    table = json.load(open(cache))
+    assert set(table) == {f"fp64/{n}" for n in ki.SWEEP_SIZES}
+    assert all(v in (4, 8) for v in table.values())
+    res2, _ = kg.kg_batch_run(runs, tune=True, tune_cache=cache)  # cached widths reused
+    for a, b in zip(res, res2):
+        assert a["blew_up"] == b["blew_up"] and a["steps_done"] == b["steps_done"]
+        assert a["E0"] == b["E0"]
+    for r, b in zip(runs, res):
+        if r["A"] < 1:
+            assert not b["blew_up"] and b["steps_done"] == 40
+
+
+def test_batch_rejects_bad_descriptors(kg):
+    with pytest.raises(kg.KGError) as e:
+        kg.kg_batch_run([dict(n=40, A=1, sigma=(1, 1, 1), dt=0.01, max_steps=5, threshold=0)])
+    assert e.value.status == kg.KG_E_UNSUPPORTED_SIZE
+    with pytest.raises(kg.KGError) as e:
+        kg.kg_batch_run([dict(n=32, A=1, sigma=(1, 0, 1), dt=0.01, max_steps=5, threshold=0)])
+    assert e.value.status == kg.KG_E_INVALID
