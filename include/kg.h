@@ -215,6 +215,48 @@ kg_status kg_batch_run(const kg_run_desc *runs, int nruns, kg_run_result *out,
 const char *kg_batch_last_error(void);
 
 /* ------------------------------------------------------------------------ */
+/* Blow-up surrogate: a small MLP trained on sweep results                   */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * MLP with 4 inputs (A, sx, sy, sz of the Gaussian data of kg_run_desc),
+ * two hidden layers of `hidden` GELU units and 2 outputs: a blow-up logit and
+ * a standardised log blow-up time, all in FP32 on the GPU.  Parametric
+ * blow-up studies are the paper's motivation (Sec. 1); the surrogate answers
+ * confident queries and the solver reruns the others.
+ * Parameters are a flat float array: W1 (hidden x 4), b1 (hidden),
+ * W2 (hidden x hidden), b2 (hidden), W3 (2 x hidden), b3 (2), row-major
+ * [out][in].  Inputs are standardised in the first layer with
+ * kg_mlp_set_norm (default mean 0, deviation 1).
+ * Training loss over a batch (labels y = 1 for blow-up, targets t used
+ * where y = 1):
+ *   (1/B) sum BCE(logit, y) + (1/max(1, sum y)) sum y (out2 - t)^2,
+ * minimised by Adam (beta1 0.9, beta2 0.999, eps 1e-8).
+ * All x / y / out pointers are device arrays of floats: x is B x 4,
+ * y is B x 2 (label, target), out is B x 2.
+ */
+typedef struct kg_mlp_s kg_mlp_t;
+
+size_t kg_mlp_num_params(int hidden);
+/* init_params: host array of kg_mlp_num_params(hidden) floats (copied). */
+kg_status kg_mlp_create(int hidden, int max_batch, const float *init_params, void *hip_stream,
+                        kg_mlp_t **out);
+void kg_mlp_destroy(kg_mlp_t *m);
+const char *kg_mlp_last_error(const kg_mlp_t *m);
+/* mean[4], stdev[4] (stdev > 0): host arrays. */
+kg_status kg_mlp_set_norm(kg_mlp_t *m, const float *mean, const float *stdev);
+/* Copy the parameters to a host array of kg_mlp_num_params floats. */
+kg_status kg_mlp_get_params(kg_mlp_t *m, float *host_out);
+/* Outputs for n inputs (any n; processed in chunks of max_batch). */
+kg_status kg_mlp_forward(kg_mlp_t *m, const float *d_x, int n, float *d_out);
+/* Loss and gradients of one batch (B <= max_batch); host outputs may be NULL. */
+kg_status kg_mlp_grad(kg_mlp_t *m, const float *d_x, const float *d_y, int B, float *host_loss,
+                      float *host_grads);
+/* One Adam step on one batch; *host_loss (may be NULL) gets the batch loss. */
+kg_status kg_mlp_train_step(kg_mlp_t *m, const float *d_x, const float *d_y, int B, float lr,
+                            float *host_loss);
+
+/* ------------------------------------------------------------------------ */
 /* Test and measurement hooks (not needed to run the solver).               */
 /* ------------------------------------------------------------------------ */
 

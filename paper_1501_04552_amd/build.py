@@ -7,7 +7,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libkg.so")
 SOURCES = [os.path.join(CSRC, f) for f in ("kg_api.hip", "kg_ops_f64.hip", "kg_ops_f32.hip",
-                                            "kg_batch.hip")]
+                                            "kg_batch.hip", "kg_mlp.hip")]
 HEADERS = [os.path.join(CSRC, f) for f in ("kg_fft.hpp", "kg_kernels.hpp", "kg_plan.hpp",
                                             "kg_batch.hpp")] + \
     [os.path.join(ROOT, "include", "kg.h")]

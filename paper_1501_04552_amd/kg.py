@@ -86,6 +86,15 @@ _SIGS = {
                                     ctypes.POINTER(kg_run_result), ctypes.POINTER(kg_batch_opts),
                                     _vp]),
     "kg_batch_last_error": (ctypes.c_char_p, []),
+    "kg_mlp_num_params": (ctypes.c_size_t, [ctypes.c_int]),
+    "kg_mlp_create": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _vp, _vp, _pp]),
+    "kg_mlp_destroy": (None, [_vp]),
+    "kg_mlp_last_error": (ctypes.c_char_p, [_vp]),
+    "kg_mlp_set_norm": (ctypes.c_int, [_vp, _vp, _vp]),
+    "kg_mlp_get_params": (ctypes.c_int, [_vp, _vp]),
+    "kg_mlp_forward": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp]),
+    "kg_mlp_grad": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp, _vp]),
+    "kg_mlp_train_step": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, ctypes.c_float, _vp]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -275,3 +284,56 @@ def kg_batch_run(runs, L=0.0, graph_steps=0, tune=False, tune_cache=None, stream
     res = [dict(blew_up=bool(o.blew_up), steps_done=o.steps_done, t_blowup=o.t_blowup, E0=o.E0,
                 E_final=o.E_final, max_abs_u=o.max_abs_u) for o in out]
     return res, secs.value
+
+
+def _mcheck(status, m):
+    if status != KG_OK:
+        raise KGError(status, _lib.kg_mlp_last_error(m).decode() if m else "")
+
+
+def kg_mlp_num_params(hidden):
+    return _lib.kg_mlp_num_params(hidden)
+
+
+def kg_mlp_create(hidden, max_batch, init_params, stream=None):
+    p = np.ascontiguousarray(init_params, np.float32)
+    assert p.size == kg_mlp_num_params(hidden)
+    out = ctypes.c_void_p()
+    _mcheck(_lib.kg_mlp_create(hidden, max_batch, p.ctypes.data, stream, ctypes.byref(out)), None)
+    return out.value
+
+
+def kg_mlp_destroy(m):
+    _lib.kg_mlp_destroy(m)
+
+
+def kg_mlp_set_norm(m, mean, stdev):
+    a = np.ascontiguousarray(mean, np.float32)
+    b = np.ascontiguousarray(stdev, np.float32)
+    _mcheck(_lib.kg_mlp_set_norm(m, a.ctypes.data, b.ctypes.data), m)
+
+
+def kg_mlp_get_params(m, hidden):
+    out = np.empty(kg_mlp_num_params(hidden), np.float32)
+    _mcheck(_lib.kg_mlp_get_params(m, out.ctypes.data), m)
+    return out
+
+
+def kg_mlp_forward(m, x_dev, out_dev):
+    """x_dev: float32 cuda tensor [n, 4]; out_dev: float32 cuda tensor [n, 2]."""
+    _mcheck(_lib.kg_mlp_forward(m, x_dev.data_ptr(), x_dev.shape[0], out_dev.data_ptr()), m)
+
+
+def kg_mlp_grad(m, x_dev, y_dev, hidden):
+    loss = np.empty(1, np.float32)
+    g = np.empty(kg_mlp_num_params(hidden), np.float32)
+    _mcheck(_lib.kg_mlp_grad(m, x_dev.data_ptr(), y_dev.data_ptr(), x_dev.shape[0],
+                             loss.ctypes.data, g.ctypes.data), m)
+    return float(loss[0]), g
+
+
+def kg_mlp_train_step(m, x_dev, y_dev, lr, want_loss=False):
+    loss = np.empty(1, np.float32)
+    _mcheck(_lib.kg_mlp_train_step(m, x_dev.data_ptr(), y_dev.data_ptr(), x_dev.shape[0],
+                                   ctypes.c_float(lr), loss.ctypes.data if want_loss else None), m)
+    return float(loss[0]) if want_loss else None
