@@ -46,15 +46,6 @@ bool batch_size_ok(int n)
     return n == 32 || n == 48 || n == 64 || n == 96 || n == 128;
 }
 
-// Threads per line and outer lines per workgroup of the 256-thread bodies.
-int tpl(int n) { return n % 3 == 0 ? n / 12 : n / 8; }
-long x_tasks(int n) { return ((long)n * n / 2 + 256 / tpl(n) - 1) / (256 / tpl(n)); }
-int yz_b(int n, int W)
-{
-    int b = 256 / (W * tpl(n));
-    return b < 1 ? 1 : (b < n ? b : n);
-}
-long yz_tasks(int n, int W, int ntx) { return (long)ntx * ((n + yz_b(n, W) - 1) / yz_b(n, W)); }
 
 // ---------------------------------------------------------------------------
 // Tile-width cache: a flat JSON object {"fp64/48": 8, ...}
@@ -102,39 +93,120 @@ void save_cache(const std::string &path, const std::map<std::string, int> &m)
 std::string cache_key(int n) { return "fp64/" + std::to_string(n); }
 
 // ---------------------------------------------------------------------------
-// One batch
+// One batch: runs grouped in size classes, one persistent kernel per class
 // ---------------------------------------------------------------------------
+
+struct Class;
+
+// Launchers of one (grid size, tile width).
+struct Launch {
+    void (*x)(const Class &, hipStream_t, BRun *, int mode, int want, int cube);
+    void (*y)(const Class &, hipStream_t, BRun *, int dir, int want);
+    void (*z)(const Class &, hipStream_t, BRun *, int mode, int want, int sel);
+    long (*x_tasks)();
+    long (*yz_tasks)(int ntx);
+    int x_lds, yz_lds;
+};
+
+struct Class {
+    int n = 0, W = 0;
+    const Launch *L = nullptr;
+    std::vector<int> runs;            // run indices
+    std::vector<BTask> xfull, yfull;  // full task lists (run-major)
+    std::vector<int> xoff0, zoff0;    // offsets of each run's tasks (by position in `runs`)
+    BTask *d_xt = nullptr, *d_yt = nullptr;
+    int *d_cnt = nullptr, *d_list = nullptr;
+    double *d_pa = nullptr, *d_pc = nullptr;
+    int gx = 0, gyz = 0;  // persistent grid sizes
+    int nlist = 0;        // runs in d_list
+    hipStream_t side = nullptr;
+    hipEvent_t ev = nullptr;
+    BList xl() const { return BList{d_xt, d_cnt}; }
+    BList yl() const { return BList{d_yt, d_cnt + 1}; }
+};
+
+template <int N, int W>
+struct LaunchImpl {
+    static void x(const Class &c, hipStream_t st, BRun *runs, int mode, int want, int cube)
+    {
+        dim3 g(c.gx), t(256);
+        switch (mode) {
+        case X_STEP: hipLaunchKernelGGL((kb_xpass<double, N, X_STEP>), g, t, 0, st, runs, c.xl(), c.d_pa, want, cube); break;
+        case X_REDUCE: hipLaunchKernelGGL((kb_xpass<double, N, X_REDUCE>), g, t, 0, st, runs, c.xl(), c.d_pa, want, cube); break;
+        case X_GAUSS: hipLaunchKernelGGL((kb_xpass<double, N, X_GAUSS>), g, t, 0, st, runs, c.xl(), c.d_pa, want, cube); break;
+        }
+    }
+    static void y(const Class &c, hipStream_t st, BRun *runs, int dir, int want)
+    {
+        dim3 g(c.gyz), t(256);
+        if (dir < 0)
+            hipLaunchKernelGGL((kb_ypass<double, N, W, -1>), g, t, 0, st, runs, c.yl(), want);
+        else
+            hipLaunchKernelGGL((kb_ypass<double, N, W, 1>), g, t, 0, st, runs, c.yl(), want);
+    }
+    static void z(const Class &c, hipStream_t st, BRun *runs, int mode, int want, int sel)
+    {
+        dim3 g(c.gyz), t(256);
+        switch (mode) {
+        case Z_STEP: hipLaunchKernelGGL((kb_zpass<double, N, W, Z_STEP>), g, t, 0, st, runs, c.yl(), c.d_pc, want, sel); break;
+        case Z_FWD_STATE: hipLaunchKernelGGL((kb_zpass<double, N, W, Z_FWD_STATE>), g, t, 0, st, runs, c.yl(), c.d_pc, want, sel); break;
+        case Z_START: hipLaunchKernelGGL((kb_zpass<double, N, W, Z_START>), g, t, 0, st, runs, c.yl(), c.d_pc, want, sel); break;
+        case Z_INV_STATE: hipLaunchKernelGGL((kb_zpass<double, N, W, Z_INV_STATE>), g, t, 0, st, runs, c.yl(), c.d_pc, want, sel); break;
+        case Z_PAIR: hipLaunchKernelGGL((kb_zpass<double, N, W, Z_PAIR>), g, t, 0, st, runs, c.yl(), c.d_pc, want, sel); break;
+        }
+    }
+    static long xt() { return XCfg<N>::blocks(); }
+    static long yzt(int ntx) { return (long)ntx * ((N + YZCfg<N, W>::B - 1) / YZCfg<N, W>::B); }
+    static constexpr Launch tab = {x, y, z, xt, yzt,
+                                   XCfg<N>::PPB * XCfg<N>::RS * 16,
+                                   W * YZCfg<N, W>::B * lslots<N>() * 16};
+};
+
+const Launch *launch_table(int n, int W)
+{
+    switch (n * 16 + W) {
+#define KG_TCASE(NN)                                              \
+    case NN * 16 + 4: return &LaunchImpl<NN, 4>::tab;             \
+    case NN * 16 + 8: return &LaunchImpl<NN, 8>::tab;
+        KG_TCASE(32)
+        KG_TCASE(48)
+        KG_TCASE(64)
+        KG_TCASE(96)
+        KG_TCASE(128)
+#undef KG_TCASE
+    }
+    return nullptr;
+}
 
 struct Batch {
     hipStream_t st = nullptr;
     int nruns = 0;
-    std::vector<BRun> host;       // run table (host copy)
-    std::vector<BTask> xfull, yfull;  // full task lists (run-major)
-    std::vector<int> xoff0, zoff0;    // offsets of each run's tasks in the full lists
+    std::vector<BRun> host;  // run table (host copy)
+    std::vector<Class> cls;
     void *arena = nullptr;
     BRun *d_runs = nullptr;
-    BTask *d_xt = nullptr, *d_yt = nullptr;
-    int *d_cnt = nullptr;  // [0] x tasks, [1] y/z tasks
-    double *d_pa = nullptr, *d_pc = nullptr;
-    int grid = 512;
     hipStream_t cap = nullptr;
+    hipEvent_t fork = nullptr;
     hipGraphExec_t gexec = nullptr;
     ~Batch()
     {
         if (gexec) (void)hipGraphExecDestroy(gexec);
+        for (Class &c : cls) {
+            if (c.side) (void)hipStreamDestroy(c.side);
+            if (c.ev) (void)hipEventDestroy(c.ev);
+        }
+        if (fork) (void)hipEventDestroy(fork);
         if (cap) (void)hipStreamDestroy(cap);
         if (arena) (void)hipFree(arena);
     }
-    BList xl() const { return BList{d_xt, d_cnt}; }
-    BList yl() const { return BList{d_yt, d_cnt + 1}; }
 };
 
 kg_status setup(Batch &b, const kg_run_desc *runs, int nruns, const std::vector<int> &W, double L)
 {
     b.nruns = nruns;
     b.host.assign(nruns, BRun{});
-    // twiddle tables: one per distinct n
-    std::map<int, size_t> tw_off;
+    std::map<int, size_t> tw_off;  // one twiddle table per size
+    std::map<std::pair<int, int>, int> cls_of;
     size_t off = 0;
     std::vector<size_t> qoff(nruns), s0off(nruns), s1off(nruns);
     for (int r = 0; r < nruns; ++r) {
@@ -176,33 +248,47 @@ kg_status setup(Batch &b, const kg_run_desc *runs, int nruns, const std::vector<
             tw_off[d.n] = off;
             off += up((size_t)d.n * 16);
         }
+        auto key = std::make_pair(R.n, R.W);
+        if (!cls_of.count(key)) {
+            cls_of[key] = (int)b.cls.size();
+            b.cls.emplace_back();
+            b.cls.back().n = R.n;
+            b.cls.back().W = R.W;
+            b.cls.back().L = launch_table(R.n, R.W);
+        }
+        b.cls[cls_of[key]].runs.push_back(r);
     }
-    // task lists, run-major
-    b.xoff0.assign(nruns, 0);
-    b.zoff0.assign(nruns, 0);
-    for (int r = 0; r < nruns; ++r) {
-        BRun &R = b.host[r];
-        b.xoff0[r] = (int)b.xfull.size();
-        for (long k = 0; k < x_tasks(R.n); ++k) b.xfull.push_back(BTask{r, (int)k});
-        b.zoff0[r] = (int)b.yfull.size();
-        for (long k = 0; k < yz_tasks(R.n, R.W, R.ntx); ++k) b.yfull.push_back(BTask{r, (int)k});
-        R.xoff = b.xoff0[r];
-        R.nxt = (int)x_tasks(R.n);
-        R.zoff = b.zoff0[r];
-        R.nzt = (int)yz_tasks(R.n, R.W, R.ntx);
+    // per class: task lists (run-major), partial offsets relative to the class
+    std::vector<size_t> o_xt(b.cls.size()), o_yt(b.cls.size()), o_cnt(b.cls.size()),
+        o_list(b.cls.size()), o_pa(b.cls.size()), o_pc(b.cls.size());
+    for (size_t k = 0; k < b.cls.size(); ++k) {
+        Class &c = b.cls[k];
+        for (size_t q = 0; q < c.runs.size(); ++q) {
+            BRun &R = b.host[c.runs[q]];
+            c.xoff0.push_back((int)c.xfull.size());
+            for (long t = 0; t < c.L->x_tasks(); ++t) c.xfull.push_back(BTask{c.runs[q], (int)t});
+            c.zoff0.push_back((int)c.yfull.size());
+            for (long t = 0; t < c.L->yz_tasks(R.ntx); ++t) c.yfull.push_back(BTask{c.runs[q], (int)t});
+            R.xoff = c.xoff0.back();
+            R.nxt = (int)c.L->x_tasks();
+            R.zoff = c.zoff0.back();
+            R.nzt = (int)c.L->yz_tasks(R.ntx);
+        }
+        o_xt[k] = off;
+        off += up(sizeof(BTask) * c.xfull.size());
+        o_yt[k] = off;
+        off += up(sizeof(BTask) * c.yfull.size());
+        o_cnt[k] = off;
+        off += up(2 * sizeof(int));
+        o_list[k] = off;
+        off += up(sizeof(int) * c.runs.size());
+        o_pa[k] = off;
+        off += up(2 * sizeof(double) * c.xfull.size());
+        o_pc[k] = off;
+        off += up(2 * sizeof(double) * c.yfull.size());
     }
     const size_t o_runs = off;
     off += up(sizeof(BRun) * nruns);
-    const size_t o_xt = off;
-    off += up(sizeof(BTask) * b.xfull.size());
-    const size_t o_yt = off;
-    off += up(sizeof(BTask) * b.yfull.size());
-    const size_t o_cnt = off;
-    off += up(2 * sizeof(int));
-    const size_t o_pa = off;
-    off += up(2 * sizeof(double) * b.xfull.size());
-    const size_t o_pc = off;
-    off += up(2 * sizeof(double) * b.yfull.size());
     hipError_t e = hipMalloc(&b.arena, off);
     if (e != hipSuccess) return bfail(KG_E_NOMEM, "batch arena of " + std::to_string(off) + " bytes");
     char *base = (char *)b.arena;
@@ -213,11 +299,34 @@ kg_status setup(Batch &b, const kg_run_desc *runs, int nruns, const std::vector<
         b.host[r].tw = base + tw_off[b.host[r].n];
     }
     b.d_runs = (BRun *)(base + o_runs);
-    b.d_xt = (BTask *)(base + o_xt);
-    b.d_yt = (BTask *)(base + o_yt);
-    b.d_cnt = (int *)(base + o_cnt);
-    b.d_pa = (double *)(base + o_pa);
-    b.d_pc = (double *)(base + o_pc);
+    int cus = 256, dev = 0, lds_cu = 160 * 1024;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev);
+    for (size_t k = 0; k < b.cls.size(); ++k) {
+        Class &c = b.cls[k];
+        c.d_xt = (BTask *)(base + o_xt[k]);
+        c.d_yt = (BTask *)(base + o_yt[k]);
+        c.d_cnt = (int *)(base + o_cnt[k]);
+        c.d_list = (int *)(base + o_list[k]);
+        c.d_pa = (double *)(base + o_pa[k]);
+        c.d_pc = (double *)(base + o_pc[k]);
+        c.nlist = (int)c.runs.size();
+        // persistent grids: as many 256-thread workgroups as the LDS lets a CU
+        // hold (reductions add ~2 KB), at most 4 per CU, no more than the tasks
+        auto grid = [&](int lds, long tasks) {
+            const int per_cu = std::max(1, std::min(4, lds_cu / (lds + 2048)));
+            return (int)std::max(1L, std::min((long)per_cu * cus, tasks));
+        };
+        c.gx = grid(c.L->x_lds, (long)c.xfull.size());
+        c.gyz = grid(c.L->yz_lds, (long)c.yfull.size());
+        const int cnt[2] = {(int)c.xfull.size(), (int)c.yfull.size()};
+        BCHK(hipMemcpyAsync(c.d_xt, c.xfull.data(), sizeof(BTask) * c.xfull.size(), hipMemcpyHostToDevice, b.st));
+        BCHK(hipMemcpyAsync(c.d_yt, c.yfull.data(), sizeof(BTask) * c.yfull.size(), hipMemcpyHostToDevice, b.st));
+        BCHK(hipMemcpyAsync(c.d_cnt, cnt, sizeof cnt, hipMemcpyHostToDevice, b.st));
+        BCHK(hipMemcpyAsync(c.d_list, c.runs.data(), sizeof(int) * c.runs.size(), hipMemcpyHostToDevice, b.st));
+        BCHK(hipStreamSynchronize(b.st));
+    }
     for (auto &kv : tw_off) {
         const int n = kv.first;
         std::vector<double> tw(2 * (size_t)n);
@@ -230,92 +339,73 @@ kg_status setup(Batch &b, const kg_run_desc *runs, int nruns, const std::vector<
                             hipMemcpyHostToDevice, b.st));
         BCHK(hipStreamSynchronize(b.st));
     }
-    const int cnt[2] = {(int)b.xfull.size(), (int)b.yfull.size()};
     BCHK(hipMemcpyAsync(b.d_runs, b.host.data(), sizeof(BRun) * nruns, hipMemcpyHostToDevice, b.st));
-    BCHK(hipMemcpyAsync(b.d_xt, b.xfull.data(), sizeof(BTask) * b.xfull.size(), hipMemcpyHostToDevice, b.st));
-    BCHK(hipMemcpyAsync(b.d_yt, b.yfull.data(), sizeof(BTask) * b.yfull.size(), hipMemcpyHostToDevice, b.st));
-    BCHK(hipMemcpyAsync(b.d_cnt, cnt, sizeof cnt, hipMemcpyHostToDevice, b.st));
     BCHK(hipStreamSynchronize(b.st));
-    int cus = 256, dev = 0;
-    (void)hipGetDevice(&dev);
-    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    b.grid = 2 * cus;  // two 56 KB-LDS workgroups fit a CU
     return KG_OK;
 }
 
-void launch_x(Batch &b, hipStream_t st, int mode, int want, int cube)
+void launch_fin(Batch &b, const Class &c, hipStream_t st, int mode, int want)
 {
-    dim3 g(b.grid), t(256);
-    switch (mode) {
-    case X_STEP: hipLaunchKernelGGL((kb_xpass<double, X_STEP>), g, t, 0, st, b.d_runs, b.xl(), b.d_pa, want, cube); break;
-    case X_REDUCE: hipLaunchKernelGGL((kb_xpass<double, X_REDUCE>), g, t, 0, st, b.d_runs, b.xl(), b.d_pa, want, cube); break;
-    case X_GAUSS: hipLaunchKernelGGL((kb_xpass<double, X_GAUSS>), g, t, 0, st, b.d_runs, b.xl(), b.d_pa, want, cube); break;
-    }
-}
-void launch_y(Batch &b, hipStream_t st, int dir, int want)
-{
-    dim3 g(b.grid), t(256);
-    if (dir < 0)
-        hipLaunchKernelGGL((kb_ypass<double, -1>), g, t, 0, st, b.d_runs, b.yl(), want);
-    else
-        hipLaunchKernelGGL((kb_ypass<double, 1>), g, t, 0, st, b.d_runs, b.yl(), want);
-}
-void launch_z(Batch &b, hipStream_t st, int mode, int want, int sel)
-{
-    dim3 g(b.grid), t(256);
-    switch (mode) {
-    case Z_STEP: hipLaunchKernelGGL((kb_zpass<double, Z_STEP>), g, t, 0, st, b.d_runs, b.yl(), b.d_pc, want, sel, 0); break;
-    case Z_FWD_STATE: hipLaunchKernelGGL((kb_zpass<double, Z_FWD_STATE>), g, t, 0, st, b.d_runs, b.yl(), b.d_pc, want, sel, 0); break;
-    case Z_START: hipLaunchKernelGGL((kb_zpass<double, Z_START>), g, t, 0, st, b.d_runs, b.yl(), b.d_pc, want, sel, 0); break;
-    case Z_INV_STATE: hipLaunchKernelGGL((kb_zpass<double, Z_INV_STATE>), g, t, 0, st, b.d_runs, b.yl(), b.d_pc, want, sel, 0); break;
-    case Z_PAIR: hipLaunchKernelGGL((kb_zpass<double, Z_PAIR>), g, t, 0, st, b.d_runs, b.yl(), b.d_pc, want, sel, 0); break;
-    }
-}
-void launch_fin(Batch &b, hipStream_t st, int mode, int want)
-{
-    const int g = std::min(b.nruns, 2048);
-    hipLaunchKernelGGL(kb_finalize, dim3(g), dim3(256), 0, st, b.d_runs, b.nruns, b.d_pa, b.d_pc, mode, want);
+    const int g = std::max(1, std::min(c.nlist, 1024));
+    hipLaunchKernelGGL(kb_finalize, dim3(g), dim3(256), 0, st, b.d_runs, c.d_list, c.nlist, c.d_pa,
+                       c.d_pc, mode, want);
 }
 
 // Initial levels, energy of the initial pair and the first working field.
 kg_status init(Batch &b)
 {
     hipStream_t st = b.st;
-    launch_x(b, st, X_GAUSS, 0, 1);  // N^0 = F[u0^3] -> S1
-    launch_y(b, st, -1, 0);
-    launch_z(b, st, Z_FWD_STATE, 0, 1);
-    launch_x(b, st, X_GAUSS, 0, 0);  // v^0 = F[u0] -> S0
-    launch_y(b, st, -1, 0);
-    launch_z(b, st, Z_FWD_STATE, 0, 2);
-    launch_z(b, st, Z_START, 0, 5);  // v^{-1} (u_t = 0) -> S1
-    launch_z(b, st, Z_PAIR, 0, 5);   // linear energy of (v^{-1}, v^0)
-    launch_z(b, st, Z_INV_STATE, 0, 3);  // Q4 of u^{-1}
-    launch_y(b, st, 1, 0);
-    launch_x(b, st, X_REDUCE, 0, 0);
-    launch_fin(b, st, BF_INIT, 0);
-    launch_z(b, st, Z_INV_STATE, 0, 4);  // working field of v^0
-    launch_y(b, st, 1, 0);
+    for (const Class &c : b.cls) {
+        const Launch &L = *c.L;
+        L.x(c, st, b.d_runs, X_GAUSS, 0, 1);  // N^0 = F[u0^3] -> S1
+        L.y(c, st, b.d_runs, -1, 0);
+        L.z(c, st, b.d_runs, Z_FWD_STATE, 0, 1);
+        L.x(c, st, b.d_runs, X_GAUSS, 0, 0);  // v^0 = F[u0] -> S0
+        L.y(c, st, b.d_runs, -1, 0);
+        L.z(c, st, b.d_runs, Z_FWD_STATE, 0, 2);
+        L.z(c, st, b.d_runs, Z_START, 0, 5);  // v^{-1} (u_t = 0) -> S1
+        L.z(c, st, b.d_runs, Z_PAIR, 0, 5);   // linear energy of (v^{-1}, v^0)
+        L.z(c, st, b.d_runs, Z_INV_STATE, 0, 3);  // Q4 of u^{-1}
+        L.y(c, st, b.d_runs, 1, 0);
+        L.x(c, st, b.d_runs, X_REDUCE, 0, 0);
+        launch_fin(b, c, st, BF_INIT, 0);
+        L.z(c, st, b.d_runs, Z_INV_STATE, 0, 4);  // working field of v^0
+        L.y(c, st, b.d_runs, 1, 0);
+    }
     BCHK(hipGetLastError());
     return KG_OK;
 }
 
-void enqueue_steps(Batch &b, hipStream_t st, int nsteps)
+void enqueue_steps(Batch &b, const Class &c, hipStream_t st, int nsteps)
 {
+    const Launch &L = *c.L;
     for (int i = 0; i < nsteps; ++i) {
-        launch_x(b, st, X_STEP, 0, 0);
-        launch_y(b, st, -1, 0);
-        launch_z(b, st, Z_STEP, 0, 0);
-        launch_y(b, st, 1, 0);
-        launch_fin(b, st, BF_STEP, 0);
+        L.x(c, st, b.d_runs, X_STEP, 0, 0);
+        L.y(c, st, b.d_runs, -1, 0);
+        L.z(c, st, b.d_runs, Z_STEP, 0, 0);
+        L.y(c, st, b.d_runs, 1, 0);
+        launch_fin(b, c, st, BF_STEP, 0);
     }
 }
 
+// G steps of every size class as concurrent branches of one graph.
 kg_status make_graph(Batch &b, int G)
 {
     BCHK(hipStreamCreateWithFlags(&b.cap, hipStreamNonBlocking));
+    BCHK(hipEventCreateWithFlags(&b.fork, hipEventDisableTiming));
+    for (Class &c : b.cls) {
+        BCHK(hipStreamCreateWithFlags(&c.side, hipStreamNonBlocking));
+        BCHK(hipEventCreateWithFlags(&c.ev, hipEventDisableTiming));
+    }
     hipGraph_t g = nullptr;
     BCHK(hipStreamBeginCapture(b.cap, hipStreamCaptureModeThreadLocal));
-    enqueue_steps(b, b.cap, G);
+    BCHK(hipEventRecord(b.fork, b.cap));
+    for (Class &c : b.cls) {
+        BCHK(hipStreamWaitEvent(c.side, b.fork, 0));
+        enqueue_steps(b, c, c.side, G);
+        BCHK(hipEventRecord(c.ev, c.side));
+        BCHK(hipStreamWaitEvent(b.cap, c.ev, 0));
+    }
     BCHK(hipStreamEndCapture(b.cap, &g));
     hipError_t e = hipGraphInstantiate(&b.gexec, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
@@ -332,24 +422,31 @@ kg_status compact(Batch &b, int want, int &nsel)
 {
     BCHK(hipMemcpyAsync(b.host.data(), b.d_runs, sizeof(BRun) * b.nruns, hipMemcpyDeviceToHost, b.st));
     BCHK(hipStreamSynchronize(b.st));
-    std::vector<BTask> xt, yt;
     nsel = 0;
-    for (int r = 0; r < b.nruns; ++r) {
-        BRun &R = b.host[r];
-        if (R.flag != want) continue;
-        ++nsel;
-        const int nx = R.nxt, nz = R.nzt;
-        R.xoff = (int)xt.size();
-        xt.insert(xt.end(), b.xfull.begin() + b.xoff0[r], b.xfull.begin() + b.xoff0[r] + nx);
-        R.zoff = (int)yt.size();
-        yt.insert(yt.end(), b.yfull.begin() + b.zoff0[r], b.yfull.begin() + b.zoff0[r] + nz);
+    for (Class &c : b.cls) {
+        std::vector<BTask> xt, yt;
+        std::vector<int> list;
+        for (size_t q = 0; q < c.runs.size(); ++q) {
+            BRun &R = b.host[c.runs[q]];
+            if (R.flag != want) continue;
+            list.push_back(c.runs[q]);
+            R.xoff = (int)xt.size();
+            xt.insert(xt.end(), c.xfull.begin() + c.xoff0[q], c.xfull.begin() + c.xoff0[q] + R.nxt);
+            R.zoff = (int)yt.size();
+            yt.insert(yt.end(), c.yfull.begin() + c.zoff0[q], c.yfull.begin() + c.zoff0[q] + R.nzt);
+        }
+        nsel += (int)list.size();
+        // the finalize grid reads nlist; the full list stays allocated
+        c.nlist = (int)list.size();
+        const int cnt[2] = {(int)xt.size(), (int)yt.size()};
+        if (!xt.empty())
+            BCHK(hipMemcpyAsync(c.d_xt, xt.data(), sizeof(BTask) * xt.size(), hipMemcpyHostToDevice, b.st));
+        if (!yt.empty())
+            BCHK(hipMemcpyAsync(c.d_yt, yt.data(), sizeof(BTask) * yt.size(), hipMemcpyHostToDevice, b.st));
+        if (!list.empty())
+            BCHK(hipMemcpyAsync(c.d_list, list.data(), sizeof(int) * list.size(), hipMemcpyHostToDevice, b.st));
+        BCHK(hipMemcpyAsync(c.d_cnt, cnt, sizeof cnt, hipMemcpyHostToDevice, b.st));
     }
-    const int cnt[2] = {(int)xt.size(), (int)yt.size()};
-    if (!xt.empty())
-        BCHK(hipMemcpyAsync(b.d_xt, xt.data(), sizeof(BTask) * xt.size(), hipMemcpyHostToDevice, b.st));
-    if (!yt.empty())
-        BCHK(hipMemcpyAsync(b.d_yt, yt.data(), sizeof(BTask) * yt.size(), hipMemcpyHostToDevice, b.st));
-    BCHK(hipMemcpyAsync(b.d_cnt, cnt, sizeof cnt, hipMemcpyHostToDevice, b.st));
     BCHK(hipMemcpyAsync(b.d_runs, b.host.data(), sizeof(BRun) * b.nruns, hipMemcpyHostToDevice, b.st));
     BCHK(hipStreamSynchronize(b.st));
     return KG_OK;
@@ -365,12 +462,16 @@ kg_status run_batch(const kg_run_desc *runs, int nruns, const std::vector<int> &
     if (s != KG_OK) return s;
     if ((s = init(b)) != KG_OK) return s;
     BCHK(hipStreamSynchronize(st));
-    if ((s = make_graph(b, G)) != KG_OK) return s;
     int max_steps = 0;
     for (int r = 0; r < nruns; ++r) max_steps = std::max(max_steps, runs[r].max_steps);
     const auto t0 = std::chrono::steady_clock::now();
-    int active = 0, tasks_live = (int)b.yfull.size();
+    int active = 0;
     if ((s = compact(b, 0, active)) != KG_OK) return s;
+    // the graph reads the finalize grids' run counts at capture: capture after
+    // the first compaction, and recapture whenever a compaction changes them
+    if ((s = make_graph(b, G)) != KG_OK) return s;
+    long tasks_live = 0;
+    for (const Class &c : b.cls) tasks_live += (long)c.nlist;
     long done = 0;
     while (active > 0 && done < max_steps) {
         const int left = max_steps - (int)done;
@@ -378,23 +479,32 @@ kg_status run_batch(const kg_run_desc *runs, int nruns, const std::vector<int> &
             BCHK(hipGraphLaunch(b.gexec, st));
             done += G;
         } else {
-            enqueue_steps(b, st, left);
+            for (const Class &c : b.cls) enqueue_steps(b, c, st, left);
             BCHK(hipGetLastError());
             done += left;
         }
-        // drop retired runs from the task lists once enough of them are gone
         BCHK(hipMemcpyAsync(b.host.data(), b.d_runs, sizeof(BRun) * nruns, hipMemcpyDeviceToHost, st));
         BCHK(hipStreamSynchronize(st));
-        int live_tasks = 0, a = 0;
-        for (int r = 0; r < nruns; ++r)
-            if (b.host[r].flag == 0) {
-                ++a;
-                live_tasks += b.host[r].nzt;
-            }
+        int a = 0;
+        for (int r = 0; r < nruns; ++r) a += b.host[r].flag == 0;
         active = a;
-        if (active > 0 && live_tasks < 0.8 * tasks_live) {
+        // drop retired runs from the task lists once enough of them are gone
+        if (active > 0 && active < 0.8 * tasks_live) {
             if ((s = compact(b, 0, active)) != KG_OK) return s;
-            tasks_live = live_tasks;
+            tasks_live = active;
+            (void)hipGraphExecDestroy(b.gexec);
+            b.gexec = nullptr;
+            for (Class &c : b.cls) {
+                (void)hipStreamDestroy(c.side);
+                (void)hipEventDestroy(c.ev);
+                c.side = nullptr;
+                c.ev = nullptr;
+            }
+            (void)hipEventDestroy(b.fork);
+            (void)hipStreamDestroy(b.cap);
+            b.fork = nullptr;
+            b.cap = nullptr;
+            if ((s = make_graph(b, G)) != KG_OK) return s;
         }
     }
     BCHK(hipStreamSynchronize(st));
@@ -404,8 +514,11 @@ kg_status run_batch(const kg_run_desc *runs, int nruns, const std::vector<int> &
     int fin = 0;
     if ((s = compact(b, 2, fin)) != KG_OK) return s;
     if (fin > 0) {
-        launch_x(b, st, X_REDUCE, 2, 0);
-        launch_fin(b, st, BF_FINAL, 2);
+        for (const Class &c : b.cls) {
+            if (c.nlist == 0) continue;
+            c.L->x(c, st, b.d_runs, X_REDUCE, 2, 0);
+            launch_fin(b, c, st, BF_FINAL, 2);
+        }
         BCHK(hipGetLastError());
     }
     BCHK(hipMemcpyAsync(b.host.data(), b.d_runs, sizeof(BRun) * nruns, hipMemcpyDeviceToHost, st));

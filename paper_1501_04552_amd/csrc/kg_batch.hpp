@@ -42,25 +42,6 @@ struct BList {
     int *count;
 };
 
-// Batch sizes compiled into the persistent kernels.
-#define KG_BATCH_SIZES(X) X(32) X(48) X(64) X(96) X(128)
-
-// LDS of a persistent batch workgroup: the largest x-pass rows or y/z tile
-// over the batch sizes (55.3 KB for the 3*2^a sizes in FP64).
-constexpr int batch_lds_bytes() { return 56 * 1024; }
-
-template <typename T, int N>
-constexpr bool x_fits()
-{
-    return XCfg<N>::NT == 256 && XCfg<N>::PPB * XCfg<N>::RS * (int)sizeof(cx<T>) <= batch_lds_bytes();
-}
-template <typename T, int N, int W>
-constexpr bool yz_fits()
-{
-    return YZCfg<N, W>::NT == 256 &&
-           W * YZCfg<N, W>::B * lslots<N>() * (int)sizeof(cx<T>) <= batch_lds_bytes();
-}
-
 template <typename T>
 __device__ __forceinline__ XArgs<T> x_args(const BRun &R, double *part)
 {
@@ -126,11 +107,18 @@ __device__ __forceinline__ ZArgs<T> z_args(const BRun &R, int sel, double *part)
     return a;
 }
 
-// x pass over all tasks of runs whose flag equals `want`.
-template <typename T, int MODE>
-__global__ __launch_bounds__(256) void kb_xpass(BRun *runs, BList L, double *part, int want, int cube)
+// Persistent passes over the tasks of all runs of one grid size N (one
+// kernel per size keeps each size's register and LDS budget its own); the
+// sizes of a sweep run as concurrent branches of one graph.  Waves per SIMD
+// requested per size: as many as the LDS allows without register spills
+// (measured with the compiler's resource report).
+template <int N>
+constexpr int batch_waves() { return N == 64 ? 4 : N == 128 ? 3 : 2; }
+template <typename T, int N, int MODE>
+__global__ __launch_bounds__(256, batch_waves<N>()) void kb_xpass(BRun *runs, BList L, double *part, int want, int cube)
 {
-    __shared__ __align__(16) unsigned char smem[batch_lds_bytes()];
+    static_assert(XCfg<N>::NT == 256, "batch workgroups have 256 threads");
+    __shared__ cx<T> rows[XCfg<N>::PPB * XCfg<N>::RS];
     const int cnt = *L.count;
     for (int i = blockIdx.x; i < cnt; i += gridDim.x) {
         const BTask tk = L.tasks[i];
@@ -138,64 +126,37 @@ __global__ __launch_bounds__(256) void kb_xpass(BRun *runs, BList L, double *par
         if (R.flag != want) continue;
         XArgs<T> a = x_args<T>(R, part + 2 * i);
         if (MODE == X_GAUSS) a.chi = cube ? (T)1 : (T)0;  // cube the sampled data or not
-        switch (R.n) {
-#define KG_XCASE(NN)                                                                    \
-    case NN:                                                                            \
-        static_assert(x_fits<T, NN>(), "x body does not fit the batch workgroup");     \
-        xbody<T, NN, MODE>(a, tk.blk, (cx<T> *)smem, part + 2 * i);                     \
-        break;
-            KG_BATCH_SIZES(KG_XCASE)
-#undef KG_XCASE
-        }
+        xbody<T, N, MODE>(a, tk.blk, rows, part + 2 * i);
         __syncthreads();  // the next task reuses the LDS
     }
 }
 
-template <typename T, int DIR>
+template <typename T, int N, int W, int DIR>
 __global__ __launch_bounds__(256) void kb_ypass(BRun *runs, BList L, int want)
 {
-    __shared__ __align__(16) unsigned char smem[batch_lds_bytes()];
+    static_assert(YZCfg<N, W>::NT == 256, "batch workgroups have 256 threads");
+    __shared__ cx<T> lds[W * YZCfg<N, W>::B * lslots<N>()];
     const int cnt = *L.count;
     for (int i = blockIdx.x; i < cnt; i += gridDim.x) {
         const BTask tk = L.tasks[i];
         const BRun &R = runs[tk.run];
         if (R.flag != want) continue;
-        const YArgs<T> a = y_args<T>(R);
-        const int key = R.n * 16 + R.W;
-        switch (key) {
-#define KG_YCASE(NN)                                                                    \
-    case NN * 16 + 4:                                                                   \
-        static_assert(yz_fits<T, NN, 4>() && yz_fits<T, NN, 8>(), "y/z tile too large"); \
-        ybody<T, NN, 4, DIR>(a, tk.blk, (cx<T> *)smem);                                 \
-        break;                                                                          \
-    case NN * 16 + 8: ybody<T, NN, 8, DIR>(a, tk.blk, (cx<T> *)smem); break;
-            KG_BATCH_SIZES(KG_YCASE)
-#undef KG_YCASE
-        }
+        ybody<T, N, W, DIR>(y_args<T>(R), tk.blk, lds);
         __syncthreads();
     }
 }
 
-template <typename T, int MODE>
-__global__ __launch_bounds__(256) void kb_zpass(BRun *runs, BList L, double *part, int want, int sel,
-                                                int has_vel)
+template <typename T, int N, int W, int MODE>
+__global__ __launch_bounds__(256, batch_waves<N>()) void kb_zpass(BRun *runs, BList L, double *part, int want, int sel)
 {
-    __shared__ __align__(16) unsigned char smem[batch_lds_bytes()];
+    static_assert(YZCfg<N, W>::NT == 256, "batch workgroups have 256 threads");
+    __shared__ cx<T> lds[W * YZCfg<N, W>::B * lslots<N>()];
     const int cnt = *L.count;
     for (int i = blockIdx.x; i < cnt; i += gridDim.x) {
         const BTask tk = L.tasks[i];
         const BRun &R = runs[tk.run];
         if (R.flag != want) continue;
-        ZArgs<T> a = z_args<T>(R, sel, part + 2 * i);
-        a.has_vel = has_vel;
-        const int key = R.n * 16 + R.W;
-        switch (key) {
-#define KG_ZCASE(NN)                                                                    \
-    case NN * 16 + 4: zbody<T, NN, 4, MODE>(a, tk.blk, (cx<T> *)smem, part + 2 * i); break; \
-    case NN * 16 + 8: zbody<T, NN, 8, MODE>(a, tk.blk, (cx<T> *)smem, part + 2 * i); break;
-            KG_BATCH_SIZES(KG_ZCASE)
-#undef KG_ZCASE
-        }
+        zbody<T, N, W, MODE>(z_args<T>(R, sel, part + 2 * i), tk.blk, lds, part + 2 * i);
         __syncthreads();
     }
 }
@@ -207,12 +168,15 @@ __global__ __launch_bounds__(256) void kb_zpass(BRun *runs, BList L, double *par
 //   mode 2 (final): Q4 of the last level of a finished run -> E_final.
 enum BFin { BF_STEP = 0, BF_INIT = 1, BF_FINAL = 2 };
 
-__global__ __launch_bounds__(256) void kb_finalize(BRun *runs, int nruns, const double *partA,
-                                                   const double *partC, int mode, int want)
+// `list` holds the run indices of one size class; the partial offsets of its
+// runs refer to that class's task lists.
+__global__ __launch_bounds__(256) void kb_finalize(BRun *runs, const int *list, int nlist,
+                                                   const double *partA, const double *partC, int mode,
+                                                   int want)
 {
     __shared__ double red[3][256];
-    for (int r = blockIdx.x; r < nruns; r += gridDim.x) {
-        BRun &R = runs[r];
+    for (int q = blockIdx.x; q < nlist; q += gridDim.x) {
+        BRun &R = runs[list[q]];
         if (R.flag != want) continue;
         double mx = 0.0, s4 = 0.0, se = 0.0;
         for (int i = threadIdx.x; i < R.nxt; i += 256) {
