@@ -9,6 +9,7 @@ import ctypes
 import os
 
 import numpy as np
+import torch  # noqa: F401  (load PyTorch's HIP runtime before the library)
 
 from .build import LIB
 

@@ -149,3 +149,57 @@ def evaluate(model, X, blown, tb, solver_seconds, n=64, dt=0.005, max_steps=2000
         "speedup": solver_seconds / (t_infer + t_rerun),
         "seconds": {"solver_all": solver_seconds, "inference": t_infer, "solver_deferred": t_rerun},
     }
+
+
+def main(argv=None):
+    """Full pipeline: label a training sweep and a held-out sweep with the
+    solver, train the MLP, evaluate it with solver fallback; prints JSON."""
+    import argparse
+    import json
+    import sys
+
+    import kg_inputs as ki
+
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--train", type=int, default=8192)
+    ap.add_argument("--test", type=int, default=1024)
+    ap.add_argument("--n", type=int, default=64)
+    ap.add_argument("--dt", type=float, default=0.005)
+    ap.add_argument("--max-steps", type=int, default=2000)
+    ap.add_argument("--epochs", type=int, default=300)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--save", default=None, help="write the labelled sweeps to this .npz")
+    args = ap.parse_args(argv)
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    cfg = dict(n=args.n, dt=args.dt, max_steps=args.max_steps, threshold=1e3)
+    Xtr = ki.surrogate_params(args.train, seed=1)
+    Xte = ki.surrogate_params(args.test, seed=2)
+    log(f"labelling {args.train} training runs at {args.n}^3")
+    btr, ttr, s_tr = sweep_labels(Xtr, log=log, **cfg)
+    log(f"labelling {args.test} held-out runs")
+    bte, tte, s_te = sweep_labels(Xte, log=log, **cfg)
+    if args.save:
+        np.savez(args.save, Xtr=Xtr, btr=btr, ttr=ttr, Xte=Xte, bte=bte, tte=tte)
+    model = Surrogate(seed=0)
+    log("training")
+    hist, t_train = model.fit(Xtr, btr, ttr, epochs=args.epochs, lr=args.lr, batch=args.batch,
+                              seed=0, log=log)
+    res = evaluate(model, Xte, bte, tte, s_te, **cfg)
+    model.close()
+    res.update({"workload": f"train {args.train} runs (seed 1), held out {args.test} (seed 2), "
+                            f"{args.n}^3, dt={args.dt}, <= {args.max_steps} steps, blow-up at "
+                            "max|u| > 1e3; MLP 4-128-128-2 GELU FP32, Adam lr "
+                            f"{args.lr}, batch {args.batch}, {args.epochs} epochs",
+                "blown_fraction_train": float(btr.mean()), "blown_fraction_test": float(bte.mean()),
+                "label_seconds_train": s_tr, "train_seconds": t_train,
+                "loss_first_last": [hist[0], hist[-1]]})
+    print(json.dumps(res), flush=True)
+    return res
+
+
+if __name__ == "__main__":
+    main()
