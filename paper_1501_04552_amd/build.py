@@ -19,7 +19,7 @@ FLAGS = [
     # packed fp32 instructions are kept out of all device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-result",
-]
+] + os.environ.get("KG_HIPFLAGS", "").split()
 
 
 def build(verbose=False):

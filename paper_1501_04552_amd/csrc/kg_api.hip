@@ -39,6 +39,18 @@ int tile_width(int precision)
     return def;
 }
 
+// Padding, in bytes, between consecutive z planes of the working field
+// (0 when unset); a multiple of 128 so rows stay line-aligned.
+long plane_pad_bytes()
+{
+    const char *e = std::getenv("KG_PLANE_PAD");
+    if (e) {
+        const long b = std::atol(e);
+        if (b >= 0 && b % 128 == 0 && b <= (1L << 20)) return b;
+    }
+    return 0;
+}
+
 std::unique_ptr<Ops> make_ops(int n, int precision, int W)
 {
     if (precision == KG_FP64) return make_ops_f64(n, W);
@@ -56,6 +68,7 @@ bool size_ok(int n)
 
 struct Layout {
     int n, H, W, ntx, P;
+    long PZ;
     size_t esz, q, s, tw, pa, pc, sub, rec, ctl, total;
     long nA, nC;
 };
@@ -71,12 +84,12 @@ bool layout(const kg_params *p, Layout &lo)
     // kx rows padded to whole 128-byte lines and to whole tiles
     const int per_line = (int)(128 / lo.esz);
     lo.P = ((lo.ntx * lo.W + per_line - 1) / per_line) * per_line;
+    lo.PZ = (long)lo.n * lo.P + plane_pad_bytes() / (long)lo.esz;
     auto ops = make_ops(p->n, p->precision, lo.W);
     lo.nA = ops->x_blocks();
     lo.nC = ops->z_blocks(lo.ntx);
     if (lo.nC < PAIR_BLOCKS) lo.nC = PAIR_BLOCKS;
-    const size_t nn = (size_t)lo.n * lo.n;
-    lo.q = up(nn * lo.P * lo.esz);
+    lo.q = up((size_t)lo.n * lo.PZ * lo.esz);
     lo.s = up((size_t)lo.n * lo.ntx * lo.n * lo.W * lo.esz);
     lo.tw = up((size_t)lo.n * lo.esz);
     lo.pa = up((size_t)lo.nA * 2 * sizeof(double));
@@ -285,6 +298,7 @@ kg_status kg_plan(const kg_params *p, void *d_workspace, size_t ws_bytes, void *
     pl->W = lo.W;
     pl->ntx = lo.ntx;
     pl->P = lo.P;
+    pl->PZ = lo.PZ;
     pl->esz = lo.esz;
     pl->L = p->L > 0 ? p->L : 8.0 * M_PI;
     const double h = pl->L / pl->n;

@@ -155,10 +155,10 @@ struct LaunchImpl {
         case Z_PAIR: hipLaunchKernelGGL((kb_zpass<double, N, W, Z_PAIR>), g, t, 0, st, runs, c.yl(), c.d_pc, want, sel); break;
         }
     }
-    static long xt() { return XCfg<N>::blocks(); }
+    static long xt() { return XCfg<double, N>::blocks(); }
     static long yzt(int ntx) { return (long)ntx * ((N + YZCfg<N, W>::B - 1) / YZCfg<N, W>::B); }
     static constexpr Launch tab = {x, y, z, xt, yzt,
-                                   XCfg<N>::PPB * XCfg<N>::RS * 16,
+                                   XCfg<double, N>::PPB * XCfg<double, N>::RS * 16,
                                    W * YZCfg<N, W>::B * lslots<N>() * 16};
 };
 

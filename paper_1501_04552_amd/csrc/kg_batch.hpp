@@ -50,6 +50,7 @@ __device__ __forceinline__ XArgs<T> x_args(const BRun &R, double *part)
     a.tw = (const cx<T> *)R.tw;
     a.part = part;
     a.P = R.P;
+    a.PZ = (long)R.n * R.P;
     a.chi = (T)R.chi;
     a.gA = R.A;
     a.gsx = R.sx;
@@ -66,6 +67,7 @@ __device__ __forceinline__ YArgs<T> y_args(const BRun &R)
     a.Q = (cx<T> *)R.Q;
     a.tw = (const cx<T> *)R.tw;
     a.P = R.P;
+    a.PZ = (long)R.n * R.P;
     a.H = R.H;
     a.ntx = R.ntx;
     return a;
@@ -83,6 +85,7 @@ __device__ __forceinline__ ZArgs<T> z_args(const BRun &R, int sel, double *part)
     a.tw = (const cx<T> *)R.tw;
     a.part = part;
     a.P = R.P;
+    a.PZ = (long)R.n * R.P;
     a.H = R.H;
     a.ntx = R.ntx;
     a.ks2 = R.ks2;
@@ -117,8 +120,8 @@ constexpr int batch_waves() { return N == 64 ? 4 : N == 128 ? 3 : 2; }
 template <typename T, int N, int MODE>
 __global__ __launch_bounds__(256, batch_waves<N>()) void kb_xpass(BRun *runs, BList L, double *part, int want, int cube)
 {
-    static_assert(XCfg<N>::NT == 256, "batch workgroups have 256 threads");
-    __shared__ cx<T> rows[XCfg<N>::PPB * XCfg<N>::RS];
+    static_assert(XCfg<T, N>::NT == 256, "batch workgroups have 256 threads");
+    __shared__ cx<T> rows[XCfg<T, N>::PPB * XCfg<T, N>::RS];
     const int cnt = *L.count;
     for (int i = blockIdx.x; i < cnt; i += gridDim.x) {
         const BTask tk = L.tasks[i];

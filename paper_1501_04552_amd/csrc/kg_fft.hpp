@@ -167,11 +167,13 @@ struct Radix {
     static_assert(TPL * E == NL, "positions must divide evenly among threads");
 };
 
-// LDS slot of line position p: one padding slot after every 8 positions, so
-// the strided writes of the early stages spread over the LDS banks.
-__device__ __forceinline__ int lpos(int p) { return p + (p >> 3); }
-template <int NL>
-constexpr int lslots() { return NL + NL / 8; }
+// LDS slot of line position p: one padding slot after every 2^SH positions
+// (SH = 0: none), so the strided writes of the early stages spread over the
+// LDS banks.  The y and z passes interleave W lines per slot and use SH = 3.
+template <int SH = 3>
+__device__ __forceinline__ int lpos(int p) { return SH ? p + (p >> SH) : p; }
+template <int NL, int SH = 3>
+constexpr int lslots() { return SH ? NL + NL / (1 << SH) : NL; }
 
 // Synchronisation between the stages of one line: the whole workgroup
 // (lines spread over several waves) or one wave (every thread of the line,
@@ -214,7 +216,7 @@ __device__ __forceinline__ void twiddles(cx<T> (&w)[R], const cx<T> *__restrict_
 // line in an LDS buffer where consecutive slots are `ls` elements apart (the
 // line needs lslots<NL>() slots).  tw is the table exp(-2 pi i j / NTAB) with
 // NTAB = NL * twm.  Callers must make sure nobody still reads the LDS line.
-template <typename T, int NL, int DIR, int SY = SYNC_BLOCK, int S = 0>
+template <typename T, int NL, int DIR, int SY = SYNC_BLOCK, int SH = 3, int S = 0>
 __device__ __forceinline__ void fft_line(cx<T> (&v)[Radix<NL>::E], cx<T> *lds, int ls, int t,
                                          const cx<T> *__restrict__ tw, int twm)
 {
@@ -225,7 +227,7 @@ __device__ __forceinline__ void fft_line(cx<T> (&v)[Radix<NL>::E], cx<T> *lds, i
     if constexpr (S > 0) {
         stage_sync<SY>();
 #pragma unroll
-        for (int j = 0; j < E; ++j) v[j] = lds[lpos(t + j * TPL) * ls];
+        for (int j = 0; j < E; ++j) v[j] = lds[lpos<SH>(t + j * TPL) * ls];
         if constexpr (!last) stage_sync<SY>();
     }
 #pragma unroll
@@ -248,10 +250,10 @@ __device__ __forceinline__ void fft_line(cx<T> (&v)[Radix<NL>::E], cx<T> *lds, i
         } else {
             const int base = (i / L) * L * R + k;
 #pragma unroll
-            for (int s = 0; s < R; ++s) lds[lpos(base + s * L) * ls] = x[s];
+            for (int s = 0; s < R; ++s) lds[lpos<SH>(base + s * L) * ls] = x[s];
         }
     }
-    if constexpr (!last) fft_line<T, NL, DIR, SY, S + 1>(v, lds, ls, t, tw, twm);
+    if constexpr (!last) fft_line<T, NL, DIR, SY, SH, S + 1>(v, lds, ls, t, tw, twm);
 }
 
 }  // namespace kg

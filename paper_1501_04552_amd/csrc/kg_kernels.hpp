@@ -104,6 +104,7 @@ struct XArgs {
     double *part;         // X_STEP / X_REDUCE: (max|u|, sum u^4) per workgroup
     const Ctl *ctl;
     int P;                // row pitch of Q
+    long PZ;              // plane pitch of Q
     T chi;                // cubic coefficient (X_STEP; X_R2C / X_GAUSS: 1 cubes the input)
     // X_GAUSS: the input is A exp(-(x^2/sx^2 + y^2/sy^2 + z^2/sz^2)) sampled at
     // x_j = -L/2 + j L / N (same for y, z), computed in place of rin
@@ -116,21 +117,35 @@ struct XArgs {
 // (imaginary parts of X[0] and X[N/2] dropped: the fields are real), and
 // the forward transform Z' of (u1^3 + i u2^3) splits back into
 //   W1[k] = (Z'[k] + conj Z'[N-k]) / 2,  W2[k] = (Z'[k] - conj Z'[N-k]) / (2i).
-template <int N>
+#ifndef KG_ZWAVES_MAX64
+#define KG_ZWAVES_MAX64 8
+#endif
+#ifndef KG_ZWAVES_MAX32
+#define KG_ZWAVES_MAX32 4
+#endif
+#ifndef KG_XPAD_SHIFT64
+#define KG_XPAD_SHIFT64 3
+#endif
+#ifndef KG_XPAD_SHIFT32
+#define KG_XPAD_SHIFT32 0
+#endif
+template <typename T, int N>
 struct XCfg {
     static constexpr int TPL = Radix<N>::TPL;
     static constexpr int NT = 256;
     static constexpr int PPB = NT / TPL;  // line pairs per workgroup
-    static constexpr int RS = lslots<N>();
+    // LDS pad spacing of the contiguous lines
+    static constexpr int SH = sizeof(T) == 8 ? KG_XPAD_SHIFT64 : KG_XPAD_SHIFT32;
+    static constexpr int RS = lslots<N, SH>();
     static constexpr long blocks() { return ((long)N * N / 2 + PPB - 1) / PPB; }
 };
 
 // One workgroup's share of the x pass: line pairs blk*PPB .. blk*PPB+PPB-1.
-// rows: LDS of XCfg<N>::PPB * RS elements; part: the workgroup's partial slot.
+// rows: LDS of XCfg<T, N>::PPB * RS elements; part: the workgroup's partial slot.
 template <typename T, int N, int MODE>
 __device__ __forceinline__ void xbody(const XArgs<T> &a, long blk, cx<T> *rows, double *part)
 {
-    using C = XCfg<N>;
+    using C = XCfg<T, N>;
     constexpr int E = Radix<N>::E, TPL = C::TPL, PPB = C::PPB, RS = C::RS, NH = N / 2;
     // a pair's threads never span two waves, so its stages sync per wave
     constexpr int XSY = (64 % TPL == 0) ? SYNC_WAVE : SYNC_BLOCK;
@@ -178,7 +193,7 @@ __device__ __forceinline__ void xbody(const XArgs<T> &a, long blk, cx<T> *rows, 
             v[j] = mk(x1, x2);
         }
     } else {
-        const cx<T> *q1 = a.Q + (2 * pr) * a.P, *q2 = q1 + a.P;
+        const cx<T> *q1 = a.Q + (2 * pr / N) * a.PZ + (2 * pr % N) * a.P, *q2 = q1 + a.P;
 #pragma unroll
         for (int j = 0; j < E; ++j) {
             const int k = t + j * TPL;
@@ -195,7 +210,7 @@ __device__ __forceinline__ void xbody(const XArgs<T> &a, long blk, cx<T> *rows, 
             // Z = X1 + i X2 (k <= N/2), conj(X1) + i conj(X2) (k > N/2)
             v[j] = k <= NH ? mk(x1.re - x2.im, x1.im + x2.re) : mk(x1.re + x2.im, x2.re - x1.im);
         }
-        fft_line<T, N, 1, XSY>(v, r, 1, t, a.tw, 1);
+        fft_line<T, N, 1, XSY, C::SH>(v, r, 1, t, a.tw, 1);
         // v[j] = u1[m] + i u2[m], m = t + j*TPL
         if constexpr (MODE == X_C2R) {
             if (act) {
@@ -228,23 +243,23 @@ __device__ __forceinline__ void xbody(const XArgs<T> &a, long blk, cx<T> *rows, 
         }
         stage_sync<XSY>();
     }
-    fft_line<T, N, -1, XSY>(v, r, 1, t, a.tw, 1);
+    fft_line<T, N, -1, XSY, C::SH>(v, r, 1, t, a.tw, 1);
     // positions >= N/2 are the partners N-k of the outputs k = 1..N/2
     stage_sync<XSY>();
 #pragma unroll
     for (int j = 0; j < E; ++j) {
         const int k = t + j * TPL;
-        if (k >= NH) r[lpos(k)] = v[j];
+        if (k >= NH) r[lpos<C::SH>(k)] = v[j];
     }
     stage_sync<XSY>();
     if (act) {
-        cx<T> *q1 = a.Q + (2 * pr) * a.P, *q2 = q1 + a.P;
+        cx<T> *q1 = a.Q + (2 * pr / N) * a.PZ + (2 * pr % N) * a.P, *q2 = q1 + a.P;
 #pragma unroll
         for (int j = 0; j < E; ++j) {
             const int k = t + j * TPL;
             if (k <= NH) {
                 const cx<T> zk = v[j];
-                const cx<T> zm = k == 0 ? conjg(zk) : conjg(r[lpos(N - k)]);
+                const cx<T> zm = k == 0 ? conjg(zk) : conjg(r[lpos<C::SH>(N - k)]);
                 st_nt(q1 + k, scale(zk + zm, (T)0.5));
                 st_nt(q2 + k, scale(rot90<-1>(zk - zm), (T)0.5));
             }
@@ -256,7 +271,7 @@ __device__ __forceinline__ void xbody(const XArgs<T> &a, long blk, cx<T> *rows, 
 template <typename T, int N, int MODE>
 __global__ __launch_bounds__(256) void k_xpass(XArgs<T> a)
 {
-    __shared__ cx<T> rows[XCfg<N>::PPB * XCfg<N>::RS];
+    __shared__ cx<T> rows[XCfg<T, N>::PPB * XCfg<T, N>::RS];
     if constexpr (MODE == X_STEP || MODE == X_REDUCE) {
         if (a.ctl->flag) return;
     }
@@ -281,6 +296,7 @@ struct YArgs {
     const cx<T> *tw;
     const Ctl *ctl;  // NULL: no blow-up test
     int P, H, ntx;
+    long PZ;
 };
 
 // One workgroup's tile of the y pass: columns tile*W.. of B consecutive z planes.
@@ -293,7 +309,7 @@ __device__ __forceinline__ void ybody(const YArgs<T> &a, long blk, cx<T> *lds)
     const int tile = (int)(blk % a.ntx), z = (int)(blk / a.ntx) * B + b;
     const int kx = tile * W + c;
     const bool act = kx < a.H && z < N;
-    cx<T> *g = a.Q + ((long)z * N) * a.P + kx;
+    cx<T> *g = a.Q + (long)z * a.PZ + kx;
     cx<T> v[E];
 #pragma unroll
     for (int j = 0; j < E; ++j) v[j] = act ? ld_nt(g + (long)(t + j * TPL) * a.P) : mk<T>(0, 0);
@@ -346,6 +362,7 @@ struct ZArgs {
     double *part;     // Z_STEP: energy partial per workgroup
     const Ctl *ctl;
     int P, H, ntx;
+    long PZ;
     double ks2;       // (2 pi / L)^2
     double dt;
     double chi;
@@ -374,7 +391,7 @@ __device__ __forceinline__ void zbody(const ZArgs<T> &a, long blk, cx<T> *lds, d
     const int tile = (int)(blk % a.ntx), ky = (int)(blk / a.ntx) * B + b;
     const int kx = tile * W + c;
     const bool act = kx < a.H && ky < N;
-    const long zs = (long)N * a.P;
+    const long zs = a.PZ;
     cx<T> *g = a.Q + (long)ky * a.P + kx;
     const long sbase = (((long)(ky < N ? ky : 0) * a.ntx + tile) * N) * W + c;
     cx<T> *lline = lds + c + W * b;
@@ -528,8 +545,23 @@ __device__ __forceinline__ void zbody(const ZArgs<T> &a, long blk, cx<T> *lds, d
     if constexpr (MODE == Z_STEP) block_max_sum<NT>(0.0, esum, part);
 }
 
+// Waves per SIMD that the LDS of a z-pass workgroup allows (160 KiB per CU,
+// 4 SIMDs); asking the compiler for that occupancy keeps the register count
+// from being the tighter limit.
+template <typename T, int N, int W>
+constexpr int z_waves()
+{
+    using C = YZCfg<N, W>;
+    constexpr long lds = (long)sizeof(cx<T>) * W * C::B * lslots<N>() + 256;
+    constexpr int wg = (int)(163840 / lds);
+    constexpr int w = wg * (C::NT / 64) / 4;
+    constexpr int cap = sizeof(T) == 8 ? KG_ZWAVES_MAX64 : KG_ZWAVES_MAX32;
+    return w < 1 ? 1 : w > cap ? cap : w;
+}
+
 template <typename T, int N, int W, int MODE>
-__global__ __launch_bounds__((YZCfg<N, W>::NT)) void k_zpass(ZArgs<T> a)
+__global__ __launch_bounds__((YZCfg<N, W>::NT)) __attribute__((amdgpu_waves_per_eu(z_waves<T, N, W>())))
+void k_zpass(ZArgs<T> a)
 {
     using C = YZCfg<N, W>;
     __shared__ cx<T> lds[W * C::B * lslots<N>()];
@@ -602,27 +634,31 @@ __global__ __launch_bounds__(256) void k_state_to_spec(const cx<T> *S, const cx<
     }
 }
 
-// Working field Q (pitch P) <-> half spectrum of doubles (pitch H).
+// Working field Q (row pitch P, plane pitch PZ, n rows per plane) <-> half
+// spectrum of doubles (pitch H).
 template <typename T>
-__global__ __launch_bounds__(256) void k_q_to_spec(const cx<T> *Q, double *out, int P, int H, long rows)
+__global__ __launch_bounds__(256) void k_q_to_spec(const cx<T> *Q, double *out, int P, long PZ, int n,
+                                                   int H, long rows)
 {
     const long total = rows * H;
     for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < total; i += (long)gridDim.x * 256) {
         const long r = i / H;
         const int k = (int)(i % H);
-        const cx<T> v = Q[r * P + k];
+        const cx<T> v = Q[(r / n) * PZ + (r % n) * P + k];
         out[2 * i] = (double)v.re;
         out[2 * i + 1] = (double)v.im;
     }
 }
 template <typename T>
-__global__ __launch_bounds__(256) void k_spec_to_q(const double *in, cx<T> *Q, int P, int H, long rows)
+__global__ __launch_bounds__(256) void k_spec_to_q(const double *in, cx<T> *Q, int P, long PZ, int n,
+                                                   int H, long rows)
 {
     const long total = rows * P;
     for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < total; i += (long)gridDim.x * 256) {
         const long r = i / P;
         const int k = (int)(i % P);
-        Q[i] = k < H ? mk((T)in[2 * (r * H + k)], (T)in[2 * (r * H + k) + 1]) : mk<T>(0, 0);
+        Q[(r / n) * PZ + (r % n) * P + k] =
+            k < H ? mk((T)in[2 * (r * H + k)], (T)in[2 * (r * H + k) + 1]) : mk<T>(0, 0);
     }
 }
 

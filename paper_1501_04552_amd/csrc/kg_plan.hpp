@@ -20,6 +20,7 @@ struct Ops;
 struct kg_plan_s {
     kg_params p{};
     int n = 0, H = 0, W = 0, ntx = 0, P = 0;
+    long PZ = 0;  // plane pitch of Q in elements (n * P plus optional padding)
     double L = 0, h3 = 0, ks2 = 0, invM = 0, escale = 0, chi = 1;
     size_t esz = 16;
     hipStream_t stream = nullptr;
@@ -74,7 +75,7 @@ struct OpsImpl final : Ops {
     using YC = YZCfg<N, W>;
     static long yz_grid(int ntx) { return (long)ntx * ((N + YC::B - 1) / YC::B); }
 
-    long x_blocks() const override { return XCfg<N>::blocks(); }
+    long x_blocks() const override { return XCfg<T, N>::blocks(); }
     long z_blocks(int ntx) const override { return yz_grid(ntx); }
 
     void x(Plan &pl, int mode, const double *rin, double *rout, double chi,
@@ -89,8 +90,9 @@ struct OpsImpl final : Ops {
         a.part = pl.partA;
         a.ctl = pl.ctl;
         a.P = pl.P;
+        a.PZ = pl.PZ;
         a.chi = (T)chi;
-        dim3 g((unsigned)XCfg<N>::blocks()), b(256);
+        dim3 g((unsigned)XCfg<T, N>::blocks()), b(256);
         switch (mode) {
         case X_STEP: hipLaunchKernelGGL((k_xpass<T, N, X_STEP>), g, b, 0, pl.stream, a); break;
         case X_REDUCE: hipLaunchKernelGGL((k_xpass<T, N, X_REDUCE>), g, b, 0, pl.stream, a); break;
@@ -105,6 +107,7 @@ struct OpsImpl final : Ops {
         a.tw = (const cx<T> *)pl.tw;
         a.ctl = check_flag ? pl.ctl : nullptr;
         a.P = pl.P;
+        a.PZ = pl.PZ;
         a.H = pl.H;
         a.ntx = pl.ntx;
         dim3 g((unsigned)yz_grid(pl.ntx)), b(YC::NT);
@@ -125,6 +128,7 @@ struct OpsImpl final : Ops {
         a.part = pl.partC;
         a.ctl = pl.ctl;
         a.P = pl.P;
+        a.PZ = pl.PZ;
         a.H = pl.H;
         a.ntx = pl.ntx;
         a.ks2 = pl.ks2;
@@ -156,12 +160,12 @@ struct OpsImpl final : Ops {
     void q_to_spec(Plan &pl, double *out) override
     {
         hipLaunchKernelGGL((k_q_to_spec<T>), dim3(2048), dim3(256), 0, pl.stream,
-                           (const cx<T> *)pl.Q, out, pl.P, pl.H, (long)N * N);
+                           (const cx<T> *)pl.Q, out, pl.P, pl.PZ, N, pl.H, (long)N * N);
     }
     void spec_to_q(Plan &pl, const double *in) override
     {
         hipLaunchKernelGGL((k_spec_to_q<T>), dim3(2048), dim3(256), 0, pl.stream, in,
-                           (cx<T> *)pl.Q, pl.P, pl.H, (long)N * N);
+                           (cx<T> *)pl.Q, pl.P, pl.PZ, N, pl.H, (long)N * N);
     }
 };
 
