@@ -101,6 +101,30 @@ bool layout(const kg_params *p, Layout &lo)
     return true;
 }
 
+// Planes per slab of the y-inverse / x / y-forward chain of a step.  A field
+// larger than the GPU's 256 MB memory-side cache is processed in slabs of
+// about SLAB_BYTES, so that each slab stays cached from the y-inverse through
+// the x pass to the y-forward pass; smaller fields are one slab.  At 512^3 on
+// MI355X 240 MB slabs beat 200 MB (per-launch tails) and 300 MB (cache
+// misses), by 2-6%.  KG_SLAB_MB overrides the slab size (0: one slab).
+constexpr double SLAB_BYTES = 240e6;
+constexpr double CACHE_BYTES = 256e6;
+
+int slab_planes(const Layout &lo, const Ops &ops)
+{
+    const double plane = (double)lo.PZ * lo.esz;
+    double target = (double)lo.n * plane > CACHE_BYTES ? SLAB_BYTES : 0.0;
+    if (const char *e = std::getenv("KG_SLAB_MB")) target = std::atof(e) * 1e6;
+    const int q = ops.slab_quantum();
+    if (!(target > 0) || target >= lo.n * plane) return lo.n;
+    int nz = (int)(target / plane) / q * q;
+    if (nz < q) nz = q;
+    // even slabs: as many as the target size asks for, as equal as q allows
+    const int nslab = (lo.n + nz - 1) / nz;
+    nz = ((lo.n + nslab - 1) / nslab + q - 1) / q * q;
+    return nz < lo.n ? nz : lo.n;
+}
+
 kg_status fail(kg_plan_s *pl, kg_status s, const char *msg)
 {
     if (pl) pl->err = msg;
@@ -200,12 +224,26 @@ void finalize(Plan &p, int nC, double thr, int mode)
                        p.escale, p.h3, mode);
 }
 
-// Q <- inverse z and y transforms of level S (scaled by 1/M): what the x pass
-// of the next step expects.
+// Q <- inverse z transform of level S (scaled by 1/M): the resting state of
+// the working field between steps, which the next step's y-inverse pass
+// starts from.  It equals what the z pass of a step leaves for the level it
+// stores (same values, same transform), so it also restores Q after calls
+// that use Q as scratch.
 kg_status prepare_q(kg_plan_s *pl, const void *S, const void *Ssub = nullptr)
 {
     Plan &p = P(pl);
     p.ops->z(p, Z_INV_STATE, nullptr, const_cast<void *>(S), p.invM, 0, Ssub);
+    LAUNCHCHK(pl);
+    return KG_OK;
+}
+
+// Q (resting state of level S) <- the level's half spectrum inverse
+// transformed along z and y: what an x pass turns into u.
+kg_status physical_q(kg_plan_s *pl, const void *S, const void *Ssub = nullptr)
+{
+    kg_status s = prepare_q(pl, S, Ssub);
+    if (s != KG_OK) return s;
+    Plan &p = P(pl);
     p.ops->y(p, 1, false);
     LAUNCHCHK(pl);
     return KG_OK;
@@ -300,6 +338,12 @@ kg_status kg_plan(const kg_params *p, void *d_workspace, size_t ws_bytes, void *
     pl->P = lo.P;
     pl->PZ = lo.PZ;
     pl->esz = lo.esz;
+    pl->ops = make_ops(p->n, p->precision, lo.W);
+    if (!pl->ops) {
+        delete pl;
+        return KG_E_UNSUPPORTED_SIZE;
+    }
+    pl->zslab = slab_planes(lo, *pl->ops);
     pl->L = p->L > 0 ? p->L : 8.0 * M_PI;
     const double h = pl->L / pl->n;
     pl->h3 = h * h * h;
@@ -314,7 +358,6 @@ kg_status kg_plan(const kg_params *p, void *d_workspace, size_t ws_bytes, void *
     pl->nC = lo.nC;
     pl->q_bytes = lo.q;
     pl->s_bytes = lo.s;
-    pl->ops = make_ops(p->n, p->precision, lo.W);
 
     if (d_workspace) {
         pl->ws = d_workspace;
@@ -428,10 +471,10 @@ kg_status kg_set_state(kg_plan_t *plan, const double *u0, const double *aux, int
     // Energy of the initial pair: linear part of (v^{-1}, v^0) and Q4 of u^{-1}.
     if (increment(p)) {
         p.ops->pair_energy(p, S0, S1);
-        if ((s = prepare_q(plan, S0, S1)) != KG_OK) return s;
+        if ((s = physical_q(plan, S0, S1)) != KG_OK) return s;
     } else {
         p.ops->pair_energy(p, S1, S0);
-        if ((s = prepare_q(plan, S1)) != KG_OK) return s;
+        if ((s = physical_q(plan, S1)) != KG_OK) return s;
     }
     p.ops->x(p, X_REDUCE, nullptr, nullptr, 0.0);
     finalize(p, PAIR_BLOCKS, 0.0, 2);
@@ -447,20 +490,37 @@ kg_status kg_set_state(kg_plan_t *plan, const double *u0, const double *aux, int
 
 namespace {
 
-// Enqueue the kernels of step m (levels v^{m-1}, v^m -> v^{m+1}) on stream st.
-void enqueue_step(Plan &p, long m, hipStream_t st)
+// Kernel kinds of a step, in the order of kg_kernel_times.
+enum { K_X = 0, K_YF = 1, K_Z = 2, K_YI = 3, K_FIN = 4 };
+
+// Enqueue the kernels of step m (levels v^{m-1}, v^m -> v^{m+1}) on stream st:
+// per slab of z planes the inverse y pass (from the resting state), the x
+// pass and the forward y pass; then the z pass (which leaves the next
+// resting state) and the finalize.  `mark(kind)` runs after each launch
+// (timing).
+template <typename F>
+void enqueue_step(Plan &p, long m, hipStream_t st, F &&mark)
 {
     void *Sc, *Sp;
     step_levels(p, m, Sc, Sp);
     hipStream_t keep = p.stream;
     p.stream = st;
-    p.ops->x(p, X_STEP, nullptr, nullptr, p.chi);
-    p.ops->y(p, -1, true);
+    for (int z0 = 0; z0 < p.n; z0 += p.zslab) {
+        const int nz = p.n - z0 < p.zslab ? p.n - z0 : p.zslab;
+        p.ops->y(p, 1, true, z0, nz);
+        mark(K_YI);
+        p.ops->x(p, X_STEP, nullptr, nullptr, p.chi, nullptr, z0, nz);
+        mark(K_X);
+        p.ops->y(p, -1, true, z0, nz);
+        mark(K_YF);
+    }
     p.ops->z(p, Z_STEP, Sp, Sc, p.invM, 0);
-    p.ops->y(p, 1, true);
+    mark(K_Z);
     finalize(p, (int)p.ops->z_blocks(p.ntx), p.p.blowup_threshold, 0);
+    mark(K_FIN);
     p.stream = keep;
 }
+void enqueue_step(Plan &p, long m, hipStream_t st) { enqueue_step(p, m, st, [](int) {}); }
 
 constexpr int GRAPH_STEPS = 8;  // steps per captured graph (even: parity returns)
 
@@ -495,7 +555,6 @@ kg_status kg_step(kg_plan_t *plan, int nsteps, unsigned flags, int *steps_done)
     if (!plan || nsteps < 0) return KG_E_INVALID;
     Plan &p = P(plan);
     if (!p.ready) return fail(plan, KG_E_INVALID, "kg_set_state has not been called");
-    const double thr = p.p.blowup_threshold;
     const bool timed = (flags & KG_STEP_TIMED) != 0;
     if (!timed && nsteps >= GRAPH_STEPS) {
         // whole graphs of GRAPH_STEPS steps, then single steps
@@ -519,43 +578,45 @@ kg_status kg_step(kg_plan_t *plan, int nsteps, unsigned flags, int *steps_done)
         }
         return KG_OK;
     }
+    // KG_STEP_TIMED: an event after every launch; the time between an event
+    // and the next is charged to the kind of the launch in between.
+    const int nslab = (p.n + p.zslab - 1) / p.zslab;
+    const size_t per_step = (size_t)3 * nslab + 3;  // launches + 1
+    std::vector<int> kinds;
     if (timed) {
-        const size_t need = (size_t)6 * nsteps;
+        const size_t need = per_step * nsteps;
         while (p.tev.size() < need) {
             hipEvent_t e;
             HIPCHK(plan, hipEventCreate(&e));
             p.tev.push_back(e);
         }
+        kinds.reserve(need);
     }
+    hipError_t rec_err = hipSuccess;
     for (int i = 0; i < nsteps; ++i) {
-        const long m = p.steps + i;
-        void *Sc, *Sp;
-        step_levels(p, m, Sc, Sp);
-        hipEvent_t *ev = timed ? &p.tev[(size_t)6 * i] : nullptr;
-        if (timed) HIPCHK(plan, hipEventRecord(ev[0], p.stream));
-        p.ops->x(p, X_STEP, nullptr, nullptr, p.chi);
-        if (timed) HIPCHK(plan, hipEventRecord(ev[1], p.stream));
-        p.ops->y(p, -1, true);
-        if (timed) HIPCHK(plan, hipEventRecord(ev[2], p.stream));
-        p.ops->z(p, Z_STEP, Sp, Sc, p.invM, 0);
-        if (timed) HIPCHK(plan, hipEventRecord(ev[3], p.stream));
-        p.ops->y(p, 1, true);
-        if (timed) HIPCHK(plan, hipEventRecord(ev[4], p.stream));
-        finalize(p, (int)p.ops->z_blocks(p.ntx), thr, 0);
-        if (timed) HIPCHK(plan, hipEventRecord(ev[5], p.stream));
+        if (!timed) {
+            enqueue_step(p, p.steps + i, p.stream);
+            continue;
+        }
+        size_t k = per_step * i;
+        rec_err = hipEventRecord(p.tev[k++], p.stream);
+        enqueue_step(p, p.steps + i, p.stream, [&](int kind) {
+            kinds.push_back(kind);
+            if (rec_err == hipSuccess) rec_err = hipEventRecord(p.tev[k++], p.stream);
+        });
+        kinds.push_back(-1);  // no launch between this step's last event and the next step's first
+        if (rec_err != hipSuccess) return hip_fail(plan, rec_err, "hipEventRecord");
     }
     LAUNCHCHK(plan);
     p.steps += nsteps;
     if (timed) {
         HIPCHK(plan, hipStreamSynchronize(p.stream));
         for (int k = 0; k < 5; ++k) p.kt_ms[k] = 0.0;
-        for (int i = 0; i < nsteps; ++i) {
-            for (int k = 0; k < 5; ++k) {
-                float t = 0;
-                HIPCHK(plan, hipEventElapsedTime(&t, p.tev[(size_t)6 * i + k],
-                                                 p.tev[(size_t)6 * i + k + 1]));
-                p.kt_ms[k] += t;
-            }
+        for (size_t e = 0; e + 1 < per_step * nsteps; ++e) {
+            if (kinds[e] < 0) continue;
+            float t = 0;
+            HIPCHK(plan, hipEventElapsedTime(&t, p.tev[e], p.tev[e + 1]));
+            p.kt_ms[kinds[e]] += t;
         }
         for (int k = 0; k < 5; ++k) p.kt_ms[k] = nsteps ? p.kt_ms[k] / nsteps : 0.0;
         p.kt_steps = nsteps;
@@ -583,14 +644,19 @@ kg_status kg_energy(kg_plan_t *plan, double *E, double *t)
     if (!plan) return KG_E_INVALID;
     Plan &p = P(plan);
     if (!p.ready) return fail(plan, KG_E_INVALID, "kg_set_state has not been called");
-    // Q4 of the newest level from its working field (reductions only).
-    p.ops->x(p, X_REDUCE, nullptr, nullptr, 0.0);
-    finalize(p, 0, 0.0, 1);
-    LAUNCHCHK(plan);
     Ctl c;
     kg_status s = read_ctl(plan, c);
     if (s != KG_OK) return s;
     if (c.flag) return KG_BLOWUP;
+    // Q4 of the newest level: y-inverse of the resting field, an x pass with
+    // reductions only, then the resting field rebuilt from the stored level.
+    p.ops->y(p, 1, false);
+    p.ops->x(p, X_REDUCE, nullptr, nullptr, 0.0);
+    finalize(p, 0, 0.0, 1);
+    const void *S, *Ssub;
+    stored_level(p, c, 0, S, Ssub);
+    if ((s = prepare_q(plan, S, Ssub)) != KG_OK) return s;
+    HIPCHK(plan, hipStreamSynchronize(p.stream));
     const int n = c.step;
     Rec r[2];
     double elin, q4a;
@@ -653,12 +719,13 @@ kg_status kg_get_u(kg_plan_t *plan, double *u_out, int on_device)
     if (s != KG_OK) return s;
     const void *S, *Ssub;
     stored_level(p, c, 0, S, Ssub);
-    if ((s = prepare_q(plan, S, Ssub)) != KG_OK) return s;
+    if ((s = physical_q(plan, S, Ssub)) != KG_OK) return s;
     const size_t bytes = (size_t)p.n * p.n * p.n * sizeof(double);
     double *d = u_out;
     if (!on_device) HIPCHK(plan, hipMalloc((void **)&d, bytes));
     p.ops->x(p, X_C2R, nullptr, d, 0.0);
     LAUNCHCHK(plan);
+    if ((s = prepare_q(plan, S, Ssub)) != KG_OK) return s;  // resting state again
     if (!on_device) {
         HIPCHK(plan, hipMemcpyAsync(u_out, d, bytes, hipMemcpyDeviceToHost, p.stream));
         HIPCHK(plan, hipStreamSynchronize(p.stream));

@@ -88,6 +88,13 @@ __device__ __forceinline__ void block_max_sum(double mx, double sm, double *out)
     }
 }
 
+// The x and y passes load and store the working field with ordinary
+// (cached) accesses: a step runs its y-inverse / x / y-forward chain slab by
+// slab of z planes so that each slab's intermediate fields stay in the GPU's
+// memory-side cache between the three passes.  (Streaming hints there would
+// send every intermediate to HBM; the z pass, which sweeps the whole field,
+// keeps them.)
+
 // ---------------------------------------------------------------------------
 // x pass
 // ---------------------------------------------------------------------------
@@ -117,25 +124,16 @@ struct XArgs {
 // (imaginary parts of X[0] and X[N/2] dropped: the fields are real), and
 // the forward transform Z' of (u1^3 + i u2^3) splits back into
 //   W1[k] = (Z'[k] + conj Z'[N-k]) / 2,  W2[k] = (Z'[k] - conj Z'[N-k]) / (2i).
-#ifndef KG_ZWAVES_MAX64
-#define KG_ZWAVES_MAX64 8
-#endif
-#ifndef KG_ZWAVES_MAX32
-#define KG_ZWAVES_MAX32 4
-#endif
-#ifndef KG_XPAD_SHIFT64
-#define KG_XPAD_SHIFT64 3
-#endif
-#ifndef KG_XPAD_SHIFT32
-#define KG_XPAD_SHIFT32 0
-#endif
 template <typename T, int N>
 struct XCfg {
     static constexpr int TPL = Radix<N>::TPL;
     static constexpr int NT = 256;
     static constexpr int PPB = NT / TPL;  // line pairs per workgroup
-    // LDS pad spacing of the contiguous lines
-    static constexpr int SH = sizeof(T) == 8 ? KG_XPAD_SHIFT64 : KG_XPAD_SHIFT32;
+    // LDS pad spacing of the contiguous lines: one slot per 8 positions in
+    // FP64 (fewest bank conflicts), none in FP32, where the padding's index
+    // arithmetic costs more registers (82 vs 64 VGPRs: 5 vs 8 waves per
+    // SIMD) than its conflicts cost time (measured at 512^3).
+    static constexpr int SH = sizeof(T) == 8 ? 3 : 0;
     static constexpr int RS = lslots<N, SH>();
     static constexpr long blocks() { return ((long)N * N / 2 + PPB - 1) / PPB; }
 };
@@ -224,14 +222,18 @@ __device__ __forceinline__ void xbody(const XArgs<T> &a, long blk, cx<T> *rows, 
             }
             return;
         }
+        // fmax drops NaNs; a NaN value also makes the sum of fourth powers NaN
+        // (all terms are >= 0, so no inf - inf), which restores it below.
 #pragma unroll
         for (int j = 0; j < E; ++j) {
             const double u1 = (double)v[j].re, u2 = (double)v[j].im;
             if (act) {
-                mx = nanmax(mx, nanmax(fabs(u1), fabs(u2)));
-                s4 += u1 * u1 * u1 * u1 + u2 * u2 * u2 * u2;
+                mx = fmax(mx, fmax(fabs(u1), fabs(u2)));
+                const double q1 = u1 * u1, q2 = u2 * u2;
+                s4 = fma(q1, q1, fma(q2, q2, s4));
             }
         }
+        if (s4 != s4) mx = s4;
         if constexpr (MODE == X_REDUCE) {
             block_max_sum<256>(mx, s4, part);
             return;
@@ -260,16 +262,26 @@ __device__ __forceinline__ void xbody(const XArgs<T> &a, long blk, cx<T> *rows, 
             if (k <= NH) {
                 const cx<T> zk = v[j];
                 const cx<T> zm = k == 0 ? conjg(zk) : conjg(r[lpos<C::SH>(N - k)]);
-                st_nt(q1 + k, scale(zk + zm, (T)0.5));
-                st_nt(q2 + k, scale(rot90<-1>(zk - zm), (T)0.5));
+                q1[k] = scale(zk + zm, (T)0.5);
+                q2[k] = scale(rot90<-1>(zk - zm), (T)0.5);
             }
         }
     }
     if constexpr (MODE == X_STEP) block_max_sum<256>(mx, s4, part);
 }
 
+// Waves per SIMD that the LDS of an x-pass workgroup (4 waves) allows.
+template <typename T, int N>
+constexpr int x_waves()
+{
+    constexpr long lds = (long)sizeof(cx<T>) * XCfg<T, N>::PPB * XCfg<T, N>::RS + 64;
+    constexpr int wg = (int)(163840 / lds);
+    return wg < 1 ? 1 : wg > 8 ? 8 : wg;
+}
+
 template <typename T, int N, int MODE>
-__global__ __launch_bounds__(256) void k_xpass(XArgs<T> a)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(x_waves<T, N>())))
+void k_xpass(XArgs<T> a)
 {
     __shared__ cx<T> rows[XCfg<T, N>::PPB * XCfg<T, N>::RS];
     if constexpr (MODE == X_STEP || MODE == X_REDUCE) {
@@ -312,11 +324,11 @@ __device__ __forceinline__ void ybody(const YArgs<T> &a, long blk, cx<T> *lds)
     cx<T> *g = a.Q + (long)z * a.PZ + kx;
     cx<T> v[E];
 #pragma unroll
-    for (int j = 0; j < E; ++j) v[j] = act ? ld_nt(g + (long)(t + j * TPL) * a.P) : mk<T>(0, 0);
+    for (int j = 0; j < E; ++j) v[j] = act ? g[(long)(t + j * TPL) * a.P] : mk<T>(0, 0);
     fft_line<T, N, DIR>(v, lds + c + W * b, W * B, t, a.tw, 1);
     if (act) {
 #pragma unroll
-        for (int j = 0; j < E; ++j) st_nt(g + (long)(t + j * TPL) * a.P, v[j]);
+        for (int j = 0; j < E; ++j) g[(long)(t + j * TPL) * a.P] = v[j];
     }
 }
 
@@ -537,17 +549,24 @@ __device__ __forceinline__ void zbody(const ZArgs<T> &a, long blk, cx<T> *lds, d
         for (int j = 0; j < E; ++j) v[j] = act ? scale(g[(t + j * TPL) * zs], (T)a.scale) : zero;
         __syncthreads();
     }
-    fft_line<T, N, 1>(v, lline, W * B, t, a.tw, 1);
+    // Recompute the inverse transform's LDS addresses and the store addresses
+    // here rather than keep those of the forward transform and the loads live
+    // (an empty asm hides the earlier values of t and g from the compiler).
+    int ti = t;
+    asm volatile("" : "+v"(ti), "+v"(g));
+    fft_line<T, N, 1>(v, lline, W * B, ti, a.tw, 1);
     if (act) {
 #pragma unroll
-        for (int j = 0; j < E; ++j) st_nt(g + (t + j * TPL) * zs, v[j]);
+        for (int j = 0; j < E; ++j) st_nt(g + (ti + j * TPL) * zs, v[j]);
     }
     if constexpr (MODE == Z_STEP) block_max_sum<NT>(0.0, esum, part);
 }
 
 // Waves per SIMD that the LDS of a z-pass workgroup allows (160 KiB per CU,
 // 4 SIMDs); asking the compiler for that occupancy keeps the register count
-// from being the tighter limit.
+// from being the tighter limit.  FP32 stays at 4: the 1024-thread FP32 tiles
+// would need 8 (64 VGPRs, with spills) and ran slower that way, as did
+// 512-thread tiles of 16 values per thread (measured at 512^3).
 template <typename T, int N, int W>
 constexpr int z_waves()
 {
@@ -555,7 +574,7 @@ constexpr int z_waves()
     constexpr long lds = (long)sizeof(cx<T>) * W * C::B * lslots<N>() + 256;
     constexpr int wg = (int)(163840 / lds);
     constexpr int w = wg * (C::NT / 64) / 4;
-    constexpr int cap = sizeof(T) == 8 ? KG_ZWAVES_MAX64 : KG_ZWAVES_MAX32;
+    constexpr int cap = sizeof(T) == 8 ? 8 : 4;
     return w < 1 ? 1 : w > cap ? cap : w;
 }
 

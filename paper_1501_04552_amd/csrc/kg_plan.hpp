@@ -21,6 +21,7 @@ struct kg_plan_s {
     kg_params p{};
     int n = 0, H = 0, W = 0, ntx = 0, P = 0;
     long PZ = 0;  // plane pitch of Q in elements (n * P plus optional padding)
+    int zslab = 0;  // z planes per slab of the y-inverse / x / y-forward chain
     double L = 0, h3 = 0, ks2 = 0, invM = 0, escale = 0, chi = 1;
     size_t esz = 16;
     hipStream_t stream = nullptr;
@@ -53,9 +54,12 @@ constexpr int PAIR_BLOCKS = 1024;
 // Kernel launchers for one (precision, grid size, tile width).
 struct Ops {
     virtual ~Ops() = default;
+    // x and y launch over planes z0 .. z0+nz-1 (nz = 0 or n: all); partial
+    // slabs must hold whole workgroups (multiples of slab_quantum) and apply
+    // to the x pass in X_STEP / X_REDUCE only.
     virtual void x(Plan &pl, int mode, const double *rin, double *rout, double chi,
-                   const double *rin2 = nullptr) = 0;
-    virtual void y(Plan &pl, int dir, bool check_flag) = 0;
+                   const double *rin2 = nullptr, int z0 = 0, int nz = 0) = 0;
+    virtual void y(Plan &pl, int dir, bool check_flag, int z0 = 0, int nz = 0) = 0;
     virtual void z(Plan &pl, int mode, void *Sp, void *Sc, double scale, int has_vel,
                    const void *Ssub = nullptr) = 0;
     virtual void pair_energy(Plan &pl, const void *S0, const void *S1) = 0;
@@ -64,6 +68,7 @@ struct Ops {
     virtual void spec_to_q(Plan &pl, const double *in) = 0;
     virtual long x_blocks() const = 0;
     virtual long z_blocks(int ntx) const = 0;
+    virtual int slab_quantum() const = 0;  // slab sizes must be multiples of this
 };
 
 // Launchers of one precision (defined in kg_ops_f64.hip / kg_ops_f32.hip).
@@ -77,9 +82,14 @@ struct OpsImpl final : Ops {
 
     long x_blocks() const override { return XCfg<T, N>::blocks(); }
     long z_blocks(int ntx) const override { return yz_grid(ntx); }
+    int slab_quantum() const override
+    {
+        constexpr int ppb = XCfg<T, N>::PPB, b = YC::B;
+        return ppb > b ? ppb : b;  // whole x workgroups and whole y workgroups
+    }
 
     void x(Plan &pl, int mode, const double *rin, double *rout, double chi,
-           const double *rin2) override
+           const double *rin2, int z0, int nz) override
     {
         XArgs<T> a{};
         a.Q = (cx<T> *)pl.Q;
@@ -92,7 +102,14 @@ struct OpsImpl final : Ops {
         a.P = pl.P;
         a.PZ = pl.PZ;
         a.chi = (T)chi;
-        dim3 g((unsigned)XCfg<T, N>::blocks()), b(256);
+        long nb = XCfg<T, N>::blocks();
+        if (nz > 0 && nz < N && (mode == X_STEP || mode == X_REDUCE)) {
+            const long b0 = (long)z0 * (N / 2) / XCfg<T, N>::PPB;
+            nb = (long)nz * (N / 2) / XCfg<T, N>::PPB;
+            a.Q += (long)z0 * pl.PZ;
+            a.part += 2 * b0;
+        }
+        dim3 g((unsigned)nb), b(256);
         switch (mode) {
         case X_STEP: hipLaunchKernelGGL((k_xpass<T, N, X_STEP>), g, b, 0, pl.stream, a); break;
         case X_REDUCE: hipLaunchKernelGGL((k_xpass<T, N, X_REDUCE>), g, b, 0, pl.stream, a); break;
@@ -100,7 +117,7 @@ struct OpsImpl final : Ops {
         case X_C2R: hipLaunchKernelGGL((k_xpass<T, N, X_C2R>), g, b, 0, pl.stream, a); break;
         }
     }
-    void y(Plan &pl, int dir, bool check_flag) override
+    void y(Plan &pl, int dir, bool check_flag, int z0, int nz) override
     {
         YArgs<T> a{};
         a.Q = (cx<T> *)pl.Q;
@@ -110,7 +127,12 @@ struct OpsImpl final : Ops {
         a.PZ = pl.PZ;
         a.H = pl.H;
         a.ntx = pl.ntx;
-        dim3 g((unsigned)yz_grid(pl.ntx)), b(YC::NT);
+        long nb = yz_grid(pl.ntx);
+        if (nz > 0 && nz < N) {
+            a.Q += (long)z0 * pl.PZ;
+            nb = (long)pl.ntx * ((nz + YC::B - 1) / YC::B);
+        }
+        dim3 g((unsigned)nb), b(YC::NT);
         if (dir < 0)
             hipLaunchKernelGGL((k_ypass<T, N, W, -1>), g, b, 0, pl.stream, a);
         else

@@ -54,3 +54,18 @@ def test_host_side_validation():
     with pytest.raises(kg.KGError) as e:
         kg.kg_plan(kg.make_params(64, 0.0))
     assert e.value.status == kg.KG_E_INVALID
+
+
+def test_plan_setup_runs_on_the_host():
+    """kg_plan's host-side set-up (layout, launchers, slab choice) runs for
+    every size and precision before any device work; without a GPU the
+    allocation then fails cleanly."""
+    import torch
+    from paper_1501_04552_amd import kg
+    if torch.cuda.is_available():
+        pytest.skip("needs a machine without a GPU (the allocation must fail)")
+    for n in (8, 24, 48, 64, 96, 128, 192, 256, 384, 512):
+        for prec in (kg.KG_FP64, kg.KG_FP32):
+            with pytest.raises(kg.KGError) as e:
+                kg.kg_plan(kg.make_params(n, 0.01, precision=prec))
+            assert e.value.status in (kg.KG_E_NOMEM, kg.KG_E_HIP)
