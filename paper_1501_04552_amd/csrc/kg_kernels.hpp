@@ -191,16 +191,24 @@ __device__ __forceinline__ void xbody(const XArgs<T> &a, long blk, cx<T> *rows, 
             v[j] = mk(x1, x2);
         }
     } else {
-        const cx<T> *q1 = a.Q + (2 * pr / N) * a.PZ + (2 * pr % N) * a.P, *q2 = q1 + a.P;
+        // Loads are unconditional so that all of a thread's are in flight
+        // together (under a branch each would wait for its data): lanes past
+        // the last pair read pair 0 and drop the values.  Each value is read
+        // twice (as X[k] and as conj X[N-k]): cached loads.
+        const long prc = act ? pr : 0;
+        const cx<T> *q1 = a.Q + (2 * prc / N) * a.PZ + (2 * prc % N) * a.P, *q2 = q1 + a.P;
+        cx<T> l1[E], l2[E];
 #pragma unroll
         for (int j = 0; j < E; ++j) {
             const int k = t + j * TPL;
             const int m = k <= NH ? k : N - k;
-            cx<T> x1 = mk<T>(0, 0), x2 = mk<T>(0, 0);
-            if (act) {  // each value is read twice (as X[k] and as conj X[N-k]): cached loads
-                x1 = q1[m];
-                x2 = q2[m];
-            }
+            l1[j] = q1[m];
+            l2[j] = q2[m];
+        }
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+            const int k = t + j * TPL;
+            cx<T> x1 = act ? l1[j] : mk<T>(0, 0), x2 = act ? l2[j] : mk<T>(0, 0);
             if (k == 0 || k == NH) {
                 x1.im = 0;
                 x2.im = 0;
@@ -270,18 +278,8 @@ __device__ __forceinline__ void xbody(const XArgs<T> &a, long blk, cx<T> *rows, 
     if constexpr (MODE == X_STEP) block_max_sum<256>(mx, s4, part);
 }
 
-// Waves per SIMD that the LDS of an x-pass workgroup (4 waves) allows.
-template <typename T, int N>
-constexpr int x_waves()
-{
-    constexpr long lds = (long)sizeof(cx<T>) * XCfg<T, N>::PPB * XCfg<T, N>::RS + 64;
-    constexpr int wg = (int)(163840 / lds);
-    return wg < 1 ? 1 : wg > 8 ? 8 : wg;
-}
-
 template <typename T, int N, int MODE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(x_waves<T, N>())))
-void k_xpass(XArgs<T> a)
+__global__ __launch_bounds__(256) void k_xpass(XArgs<T> a)
 {
     __shared__ cx<T> rows[XCfg<T, N>::PPB * XCfg<T, N>::RS];
     if constexpr (MODE == X_STEP || MODE == X_REDUCE) {
@@ -321,10 +319,16 @@ __device__ __forceinline__ void ybody(const YArgs<T> &a, long blk, cx<T> *lds)
     const int tile = (int)(blk % a.ntx), z = (int)(blk / a.ntx) * B + b;
     const int kx = tile * W + c;
     const bool act = kx < a.H && z < N;
-    cx<T> *g = a.Q + (long)z * a.PZ + kx;
+    // planes past the last (ragged workgroups of small grids) are clamped so
+    // that the loads, issued unconditionally to be in flight together, stay
+    // in bounds; only act lanes store
+    cx<T> *g = a.Q + (long)(z < N ? z : 0) * a.PZ + kx;
     cx<T> v[E];
 #pragma unroll
-    for (int j = 0; j < E; ++j) v[j] = act ? g[(long)(t + j * TPL) * a.P] : mk<T>(0, 0);
+    for (int j = 0; j < E; ++j) {
+        const cx<T> x = g[(long)(t + j * TPL) * a.P];
+        v[j] = act ? x : mk<T>(0, 0);
+    }
     fft_line<T, N, DIR>(v, lds + c + W * b, W * B, t, a.tw, 1);
     if (act) {
 #pragma unroll
@@ -404,7 +408,10 @@ __device__ __forceinline__ void zbody(const ZArgs<T> &a, long blk, cx<T> *lds, d
     const int kx = tile * W + c;
     const bool act = kx < a.H && ky < N;
     const long zs = a.PZ;
-    cx<T> *g = a.Q + (long)ky * a.P + kx;
+    // rows past the last ky (ragged workgroups of small grids) are clamped so
+    // that every address formed stays in bounds (the state loads are
+    // unconditional); only act lanes store
+    cx<T> *g = a.Q + (long)(ky < N ? ky : 0) * a.P + kx;
     const long sbase = (((long)(ky < N ? ky : 0) * a.ntx + tile) * N) * W + c;
     cx<T> *lline = lds + c + W * b;
     const cx<T> zero = mk<T>(0, 0);
@@ -443,6 +450,8 @@ __device__ __forceinline__ void zbody(const ZArgs<T> &a, long blk, cx<T> *lds, d
     }
     if constexpr (MODE == Z_STEP || MODE == Z_FWD_STATE || MODE == Z_FWD_Q || MODE == Z_START) {
         if (MODE != Z_START || a.has_vel) {
+            // (conditional loads here measured faster than unconditional
+            // ones in FP32, and equal in FP64)
 #pragma unroll
             for (int j = 0; j < E; ++j) v[j] = act ? ld_nt(g + (t + j * TPL) * zs) : zero;
             fft_line<T, N, -1>(v, lline, W * B, t, a.tw, 1);
@@ -497,39 +506,60 @@ __device__ __forceinline__ void zbody(const ZArgs<T> &a, long blk, cx<T> *lds, d
     if constexpr (MODE == Z_STEP) {
         const double wgt = (kx == 0 || kx == N / 2) ? 1.0 : 2.0;
         const double idt2 = 1.0 / (a.dt * a.dt);
+        // The state loads of a batch of ZB positions are issued before any is
+        // used, unconditionally (the padding columns of the last tile are
+        // allocated), so they are in flight together; loads under a
+        // per-position branch would each wait for their own data before the
+        // next is issued.  FP64 batches 4 positions to stay within 128 VGPRs
+        // (1, 2 and 8 measured slower at 512^3); FP32 takes 8.
+        constexpr int ZB0 = sizeof(T) == 8 ? 4 : 8;
+        constexpr int ZB = E % ZB0 == 0 ? ZB0 : E;  // batches cover all E positions
+        static_assert(E % ZB == 0, "state-load batches must tile the positions");
 #pragma unroll
-        for (int j = 0; j < E; ++j) {
+        for (int h = 0; h < E / ZB; ++h) {
+          cx<T> vcs[ZB], vps[ZB];
+#pragma unroll
+          for (int i = 0; i < ZB; ++i) {
+              const long si = sbase + (long)(t + (h * ZB + i) * TPL) * W;
+              vcs[i] = ld_nt(a.Sc + si);
+              vps[i] = ld_nt(a.Sp + si);
+          }
+#pragma unroll
+          for (int i = 0; i < ZB; ++i) {
+            const int j = h * ZB + i;
             const int kz = t + j * TPL, mz = kz <= N / 2 ? kz : kz - N;
-            cx<T> nv = zero;
+            double al, be, w2;
+            coeffs(kx, my, mz, a.ks2, a.dt, al, be, w2);
+            const long si = sbase + (long)kz * W;
+            const cx<T> vc = vcs[i], vp = vps[i];
+            double nr, ni, dr, di;  // v^{n+1} and v^{n+1} - v^n in FP64
+            if constexpr (increment_form<T>()) {
+                // Delta^{n+1} = Delta^n - (2 - alpha) v^n + beta N^n
+                const double c2 = 2.0 - al;
+                dr = (double)vp.re - c2 * (double)vc.re + be * (double)v[j].re;
+                di = (double)vp.im - c2 * (double)vc.im + be * (double)v[j].im;
+                nr = (double)vc.re + dr;
+                ni = (double)vc.im + di;
+            } else {
+                nr = al * (double)vc.re - (double)vp.re + be * (double)v[j].re;
+                ni = al * (double)vc.im - (double)vp.im + be * (double)v[j].im;
+                dr = nr - (double)vc.re;
+                di = ni - (double)vc.im;
+            }
+            const cx<T> nv = mk((T)nr, (T)ni);
             if (act) {
-                double al, be, w2;
-                coeffs(kx, my, mz, a.ks2, a.dt, al, be, w2);
-                const long si = sbase + (long)kz * W;
-                const cx<T> vc = ld_nt(a.Sc + si), vp = ld_nt(a.Sp + si);
-                double nr, ni, dr, di;  // v^{n+1} and v^{n+1} - v^n in FP64
                 if constexpr (increment_form<T>()) {
-                    // Delta^{n+1} = Delta^n - (2 - alpha) v^n + beta N^n
-                    const double c2 = 2.0 - al;
-                    dr = (double)vp.re - c2 * (double)vc.re + be * (double)v[j].re;
-                    di = (double)vp.im - c2 * (double)vc.im + be * (double)v[j].im;
-                    nr = (double)vc.re + dr;
-                    ni = (double)vc.im + di;
-                    nv = mk((T)nr, (T)ni);
                     st_nt(a.Sc + si, nv);
                     st_nt(a.Sp + si, mk((T)dr, (T)di));
                 } else {
-                    nr = al * (double)vc.re - (double)vp.re + be * (double)v[j].re;
-                    ni = al * (double)vc.im - (double)vp.im + be * (double)v[j].im;
-                    nv = mk((T)nr, (T)ni);
                     st_nt(a.Sp + si, nv);
-                    dr = nr - (double)vc.re;
-                    di = ni - (double)vc.im;
                 }
                 const double sr = nr + (double)vc.re, sim = ni + (double)vc.im;
                 esum += wgt * ((dr * dr + di * di) * idt2 + 0.25 * w2 * (sr * sr + sim * sim));
             }
             // the stored level, scaled as a resumed run scales it (Z_INV_STATE)
-            v[j] = scale(nv, (T)a.scale);
+            v[j] = act ? scale(nv, (T)a.scale) : zero;
+          }
         }
         __syncthreads();
     } else if constexpr (MODE == Z_INV_STATE) {

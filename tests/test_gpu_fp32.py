@@ -22,7 +22,7 @@ def rel_l2(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
-@pytest.mark.parametrize("n", [8, 16, 64, 256])
+@pytest.mark.parametrize("n", [8, 16, 24, 48, 64, 96, 256])
 def test_fp32_transforms(kg, n):
     with kg.Solver(n, 0.01, precision=FP32) as s:
         u = ki.random_field(n, seed=n)
@@ -46,10 +46,13 @@ def test_fp32_small_config(kg):
     assert abs(E - ref["energy"][steps]) <= 1e-4 * abs(ref["energy"][steps])
 
 
-def test_fp32_nonlinear_against_oracle(kg):
-    """A = 1.5 Gaussian (the precision study's data) at 128^3, 200 steps."""
-    n, dt, steps = 128, 0.005, 200
-    u0 = ki.gaussian(n, 1.5)
+@pytest.mark.parametrize("n, sigma", [(128, (1.0, 1.0, 1.0)), (48, (0.8, 1.1, 1.3)), (96, (1.3, 0.9, 1.0))])
+def test_fp32_nonlinear_against_oracle(kg, n, sigma):
+    """A = 1.5 Gaussian (the precision study's data) at 128^3, and the
+    3 * 2^a grids of the sweep (radix-3 lines, 12 values per thread) with
+    anisotropic widths, 200 steps."""
+    dt, steps = 0.005, 200
+    u0 = ki.gaussian(n, 1.5, sigma)
     ref = oracle.run(u0, dt, steps)
     with kg.Solver(n, dt, precision=FP32) as s:
         s.set_state(u0)
