@@ -104,10 +104,11 @@ bool layout(const kg_params *p, Layout &lo)
 // Planes per slab of the y-inverse / x / y-forward chain of a step.  A field
 // larger than the GPU's 256 MB memory-side cache is processed in slabs of
 // about SLAB_BYTES, so that each slab stays cached from the y-inverse through
-// the x pass to the y-forward pass; smaller fields are one slab.  At 512^3 on
-// MI355X 240 MB slabs beat 200 MB (per-launch tails) and 300 MB (cache
-// misses), by 2-6%.  KG_SLAB_MB overrides the slab size (0: one slab).
-constexpr double SLAB_BYTES = 240e6;
+// the x pass to the y-forward pass; smaller fields are one slab.  Captured
+// steps run alternate slabs on two streams, so two slabs share the cache: at
+// 512^3 on MI355X 120 MB slabs measured best (one stream: 240 MB, 2% slower).
+// KG_SLAB_MB overrides the slab size (0: one slab).
+constexpr double SLAB_BYTES = 120e6;
 constexpr double CACHE_BYTES = 256e6;
 
 int slab_planes(const Layout &lo, const Ops &ops)
@@ -425,6 +426,10 @@ void kg_destroy(kg_plan_t *plan)
     for (hipGraphExec_t g : plan->gexec)
         if (g) (void)hipGraphExecDestroy(g);
     if (plan->cap) (void)hipStreamDestroy(plan->cap);
+    if (plan->cap2) (void)hipStreamDestroy(plan->cap2);
+    if (plan->side) (void)hipStreamDestroy(plan->side);
+    if (plan->ev_fork) (void)hipEventDestroy(plan->ev_fork);
+    if (plan->ev_join) (void)hipEventDestroy(plan->ev_join);
     if (plan->own_ws && plan->ws) (void)hipFree(plan->ws);
     delete plan;
 }
@@ -497,22 +502,35 @@ enum { K_X = 0, K_YF = 1, K_Z = 2, K_YI = 3, K_FIN = 4 };
 // per slab of z planes the inverse y pass (from the resting state), the x
 // pass and the forward y pass; then the z pass (which leaves the next
 // resting state) and the finalize.  `mark(kind)` runs after each launch
-// (timing).
+// (timing).  With a `side` stream the odd slabs' chains run on it, forked
+// from and joined back to st: slabs are independent, so one slab's kernels
+// fill the tail of another's (the results are the same).
 template <typename F>
-void enqueue_step(Plan &p, long m, hipStream_t st, F &&mark)
+void enqueue_step(Plan &p, long m, hipStream_t st, F &&mark, hipStream_t side = nullptr)
 {
     void *Sc, *Sp;
     step_levels(p, m, Sc, Sp);
     hipStream_t keep = p.stream;
-    p.stream = st;
-    for (int z0 = 0; z0 < p.n; z0 += p.zslab) {
+    const bool two = side && p.zslab < p.n;
+    if (two) {
+        (void)hipEventRecord(p.ev_fork, st);
+        (void)hipStreamWaitEvent(side, p.ev_fork, 0);
+    }
+    int slab = 0;
+    for (int z0 = 0; z0 < p.n; z0 += p.zslab, ++slab) {
         const int nz = p.n - z0 < p.zslab ? p.n - z0 : p.zslab;
+        p.stream = two && (slab & 1) ? side : st;
         p.ops->y(p, 1, true, z0, nz);
         mark(K_YI);
         p.ops->x(p, X_STEP, nullptr, nullptr, p.chi, nullptr, z0, nz);
         mark(K_X);
         p.ops->y(p, -1, true, z0, nz);
         mark(K_YF);
+    }
+    p.stream = st;
+    if (two) {
+        (void)hipEventRecord(p.ev_join, side);
+        (void)hipStreamWaitEvent(st, p.ev_join, 0);
     }
     p.ops->z(p, Z_STEP, Sp, Sc, p.invM, 0);
     mark(K_Z);
@@ -524,15 +542,37 @@ void enqueue_step(Plan &p, long m, hipStream_t st) { enqueue_step(p, m, st, [](i
 
 constexpr int GRAPH_STEPS = 8;  // steps per captured graph (even: parity returns)
 
+// Streams the slab chain of a captured step runs on (KG_SLAB_STREAMS, 1 or 2).
+int slab_streams()
+{
+    if (const char *e = std::getenv("KG_SLAB_STREAMS")) return std::atoi(e) > 1 ? 2 : 1;
+    return 2;
+}
+
+// The second stream of a step's slab chain (created on first use), or null
+// when the chain is one slab or KG_SLAB_STREAMS asks for one stream.
+hipStream_t slab_side(Plan &p, bool capture)
+{
+    if (slab_streams() < 2 || p.zslab >= p.n) return nullptr;
+    hipStream_t &s = capture ? p.cap2 : p.side;
+    if (!s && hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return nullptr;
+    if (!p.ev_fork && hipEventCreateWithFlags(&p.ev_fork, hipEventDisableTiming) != hipSuccess)
+        return nullptr;
+    if (!p.ev_join && hipEventCreateWithFlags(&p.ev_join, hipEventDisableTiming) != hipSuccess)
+        return nullptr;
+    return s;
+}
+
 // The graph of GRAPH_STEPS steps starting at a level of parity `par`,
 // captured once on the plan's private stream and replayed on its stream.
 kg_status step_graph(Plan &p, int par, hipGraphExec_t &out)
 {
     if (!p.gexec[par]) {
         if (!p.cap) HIPCHK(&p, hipStreamCreateWithFlags(&p.cap, hipStreamNonBlocking));
+        hipStream_t side = slab_side(p, true);
         hipGraph_t g = nullptr;
         HIPCHK(&p, hipStreamBeginCapture(p.cap, hipStreamCaptureModeThreadLocal));
-        for (int i = 0; i < GRAPH_STEPS; ++i) enqueue_step(p, par + i, p.cap);
+        for (int i = 0; i < GRAPH_STEPS; ++i) enqueue_step(p, par + i, p.cap, [](int) {}, side);
         hipError_t e = hipStreamEndCapture(p.cap, &g);
         if (e != hipSuccess) return hip_fail(&p, e, "hipStreamEndCapture");
         e = hipGraphInstantiate(&p.gexec[par], g, nullptr, nullptr, 0);
@@ -566,7 +606,8 @@ kg_status kg_step(kg_plan_t *plan, int nsteps, unsigned flags, int *steps_done)
             HIPCHK(plan, hipGraphLaunch(ge, p.stream));
             done += GRAPH_STEPS;
         }
-        for (; done < nsteps; ++done) enqueue_step(p, p.steps + done, p.stream);
+        hipStream_t side = slab_side(p, false);
+        for (; done < nsteps; ++done) enqueue_step(p, p.steps + done, p.stream, [](int) {}, side);
         LAUNCHCHK(plan);
         p.steps += nsteps;
         if (flags & KG_STEP_SYNC) {
@@ -595,7 +636,7 @@ kg_status kg_step(kg_plan_t *plan, int nsteps, unsigned flags, int *steps_done)
     hipError_t rec_err = hipSuccess;
     for (int i = 0; i < nsteps; ++i) {
         if (!timed) {
-            enqueue_step(p, p.steps + i, p.stream);
+            enqueue_step(p, p.steps + i, p.stream, [](int) {}, slab_side(p, false));
             continue;
         }
         size_t k = per_step * i;

@@ -173,31 +173,34 @@ def test_determinism_and_checkpoint(kg):
 @pytest.mark.parametrize("precision", [0, 1])
 def test_slab_chain_is_bitwise_independent_of_slab_count(kg, monkeypatch, precision):
     """Fields above the cache size step their y-inverse / x / y-forward chain
-    slab by slab of z planes; every line sees the same arithmetic, so one
-    slab, the default slabs and many ragged slabs agree bitwise (384^3:
-    2 default slabs in FP64; 10 slabs of 40 planes, the last of 24)."""
-    n, dt, steps = 384, 0.005, 6
+    slab by slab of z planes, in captured graphs on one or two streams; every
+    line sees the same arithmetic, so one slab, the default slabs and many
+    ragged slabs, on either schedule, agree bitwise (384^3: 2 default slabs in
+    FP64; 10 slabs of 40 planes, the last of 24).  Eight steps replay a graph,
+    the rest run eagerly, around an energy() call that rebuilds the field."""
+    n, dt = 384, 0.005
     u0 = ki.gaussian(n, 1.2, (0.8, 1.0, 1.3))
     out = {}
     for mb in ("0", None, "50"):
-        if mb is None:
-            monkeypatch.delenv("KG_SLAB_MB", raising=False)
-        else:
-            monkeypatch.setenv("KG_SLAB_MB", mb)
-        with kg.Solver(n, dt, precision=precision) as s:
-            s.set_state(u0)
-            s.step(steps)
-            E = s.energy()
-            s.step(2)  # energy() rebuilt the resting field: stepping goes on exactly
-            out[mb] = (s.u(), E, s.spectrum(0), s.records(0, steps + 2))
-    ref = out["0"]
-    for mb in (None, "50"):
-        got = out[mb]
-        assert np.array_equal(got[0], ref[0]), mb
-        assert got[1] == ref[1], mb
-        assert np.array_equal(got[2], ref[2]), mb
+        for streams in ("1", "2"):
+            if mb is None:
+                monkeypatch.delenv("KG_SLAB_MB", raising=False)
+            else:
+                monkeypatch.setenv("KG_SLAB_MB", mb)
+            monkeypatch.setenv("KG_SLAB_STREAMS", streams)
+            with kg.Solver(n, dt, precision=precision) as s:
+                s.set_state(u0)
+                s.step(8)
+                E = s.energy()
+                s.step(3)
+                out[(mb, streams)] = (s.u(), E, s.spectrum(0), s.records(0, 11))
+    ref = out[("0", "1")]
+    for key, got in out.items():
+        assert np.array_equal(got[0], ref[0]), key
+        assert got[1] == ref[1], key
+        assert np.array_equal(got[2], ref[2]), key
         for a, b in zip(got[3], ref[3]):
-            assert np.array_equal(a, b), mb
+            assert np.array_equal(a, b), key
 
 
 def test_first_step_at_512_sampled_modes(kg):
