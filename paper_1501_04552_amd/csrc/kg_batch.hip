@@ -92,17 +92,37 @@ void save_cache(const std::string &path, const std::map<std::string, int> &m)
 
 std::string cache_key(int n) { return "fp64/" + std::to_string(n); }
 
+// Fields per chunk of a size class (KG_BATCH_CHUNK_MB overrides; 0: the
+// whole class).  A graph replays all its steps on one chunk before the next,
+// the size classes running as concurrent branches.  On MI355X, for the
+// {48,64,96,128}^3 sweep, 400 MB chunks measured 17% faster than whole
+// classes; 50-200 MB lose to per-launch overheads, 800 MB and more to misses.
+double chunk_bytes()
+{
+    if (const char *e = std::getenv("KG_BATCH_CHUNK_MB")) return std::atof(e) * 1e6;
+    return 400e6;
+}
+
 // ---------------------------------------------------------------------------
 // One batch: runs grouped in size classes, one persistent kernel per class
 // ---------------------------------------------------------------------------
 
-struct Class;
+// The tasks one set of launches covers: a whole size class, or a chunk of
+// it (consecutive runs of the class's task lists).
+struct View {
+    BList xl, yl;       // x-pass and y/z-pass tasks (count in device memory)
+    double *pa, *pc;    // partial slots of the lists' first tasks
+    double *fa, *fc;    // the class's partial arrays (the finalize indexes them)
+    const int *list;    // run indices for the finalize
+    int nlist;
+    int gx, gyz;        // persistent grid sizes
+};
 
 // Launchers of one (grid size, tile width).
 struct Launch {
-    void (*x)(const Class &, hipStream_t, BRun *, int mode, int want, int cube);
-    void (*y)(const Class &, hipStream_t, BRun *, int dir, int want);
-    void (*z)(const Class &, hipStream_t, BRun *, int mode, int want, int sel);
+    void (*x)(const View &, hipStream_t, BRun *, int mode, int want, int cube);
+    void (*y)(const View &, hipStream_t, BRun *, int dir, int want);
+    void (*z)(const View &, hipStream_t, BRun *, int mode, int want, int sel);
     long (*x_tasks)();
     long (*yz_tasks)(int ntx);
     int x_lds, yz_lds;
@@ -119,40 +139,45 @@ struct Class {
     double *d_pa = nullptr, *d_pc = nullptr;
     int gx = 0, gyz = 0;  // persistent grid sizes
     int nlist = 0;        // runs in d_list
+    int *d_ccnt = nullptr;     // task counts of the chunks (x, y/z per chunk)
+    std::vector<View> chunks;  // the class in chunks of consecutive runs
     hipStream_t side = nullptr;
     hipEvent_t ev = nullptr;
-    BList xl() const { return BList{d_xt, d_cnt}; }
-    BList yl() const { return BList{d_yt, d_cnt + 1}; }
+    View whole() const
+    {
+        return View{BList{d_xt, d_cnt}, BList{d_yt, d_cnt + 1}, d_pa, d_pc, d_pa, d_pc, d_list, nlist,
+                    gx, gyz};
+    }
 };
 
 template <int N, int W>
 struct LaunchImpl {
-    static void x(const Class &c, hipStream_t st, BRun *runs, int mode, int want, int cube)
+    static void x(const View &c, hipStream_t st, BRun *runs, int mode, int want, int cube)
     {
         dim3 g(c.gx), t(256);
         switch (mode) {
-        case X_STEP: hipLaunchKernelGGL((kb_xpass<double, N, X_STEP>), g, t, 0, st, runs, c.xl(), c.d_pa, want, cube); break;
-        case X_REDUCE: hipLaunchKernelGGL((kb_xpass<double, N, X_REDUCE>), g, t, 0, st, runs, c.xl(), c.d_pa, want, cube); break;
-        case X_GAUSS: hipLaunchKernelGGL((kb_xpass<double, N, X_GAUSS>), g, t, 0, st, runs, c.xl(), c.d_pa, want, cube); break;
+        case X_STEP: hipLaunchKernelGGL((kb_xpass<double, N, X_STEP>), g, t, 0, st, runs, c.xl, c.pa, want, cube); break;
+        case X_REDUCE: hipLaunchKernelGGL((kb_xpass<double, N, X_REDUCE>), g, t, 0, st, runs, c.xl, c.pa, want, cube); break;
+        case X_GAUSS: hipLaunchKernelGGL((kb_xpass<double, N, X_GAUSS>), g, t, 0, st, runs, c.xl, c.pa, want, cube); break;
         }
     }
-    static void y(const Class &c, hipStream_t st, BRun *runs, int dir, int want)
+    static void y(const View &c, hipStream_t st, BRun *runs, int dir, int want)
     {
         dim3 g(c.gyz), t(256);
         if (dir < 0)
-            hipLaunchKernelGGL((kb_ypass<double, N, W, -1>), g, t, 0, st, runs, c.yl(), want);
+            hipLaunchKernelGGL((kb_ypass<double, N, W, -1>), g, t, 0, st, runs, c.yl, want);
         else
-            hipLaunchKernelGGL((kb_ypass<double, N, W, 1>), g, t, 0, st, runs, c.yl(), want);
+            hipLaunchKernelGGL((kb_ypass<double, N, W, 1>), g, t, 0, st, runs, c.yl, want);
     }
-    static void z(const Class &c, hipStream_t st, BRun *runs, int mode, int want, int sel)
+    static void z(const View &c, hipStream_t st, BRun *runs, int mode, int want, int sel)
     {
         dim3 g(c.gyz), t(256);
         switch (mode) {
-        case Z_STEP: hipLaunchKernelGGL((kb_zpass<double, N, W, Z_STEP>), g, t, 0, st, runs, c.yl(), c.d_pc, want, sel); break;
-        case Z_FWD_STATE: hipLaunchKernelGGL((kb_zpass<double, N, W, Z_FWD_STATE>), g, t, 0, st, runs, c.yl(), c.d_pc, want, sel); break;
-        case Z_START: hipLaunchKernelGGL((kb_zpass<double, N, W, Z_START>), g, t, 0, st, runs, c.yl(), c.d_pc, want, sel); break;
-        case Z_INV_STATE: hipLaunchKernelGGL((kb_zpass<double, N, W, Z_INV_STATE>), g, t, 0, st, runs, c.yl(), c.d_pc, want, sel); break;
-        case Z_PAIR: hipLaunchKernelGGL((kb_zpass<double, N, W, Z_PAIR>), g, t, 0, st, runs, c.yl(), c.d_pc, want, sel); break;
+        case Z_STEP: hipLaunchKernelGGL((kb_zpass<double, N, W, Z_STEP>), g, t, 0, st, runs, c.yl, c.pc, want, sel); break;
+        case Z_FWD_STATE: hipLaunchKernelGGL((kb_zpass<double, N, W, Z_FWD_STATE>), g, t, 0, st, runs, c.yl, c.pc, want, sel); break;
+        case Z_START: hipLaunchKernelGGL((kb_zpass<double, N, W, Z_START>), g, t, 0, st, runs, c.yl, c.pc, want, sel); break;
+        case Z_INV_STATE: hipLaunchKernelGGL((kb_zpass<double, N, W, Z_INV_STATE>), g, t, 0, st, runs, c.yl, c.pc, want, sel); break;
+        case Z_PAIR: hipLaunchKernelGGL((kb_zpass<double, N, W, Z_PAIR>), g, t, 0, st, runs, c.yl, c.pc, want, sel); break;
         }
     }
     static long xt() { return XCfg<double, N>::blocks(); }
@@ -182,6 +207,15 @@ struct Batch {
     hipStream_t st = nullptr;
     int nruns = 0;
     std::vector<BRun> host;  // run table (host copy)
+    std::vector<size_t> bytes;  // fields of each run (Q and both levels)
+    int cus = 256, lds_cu = 160 * 1024;
+    // persistent grids: as many 256-thread workgroups as the LDS lets a CU
+    // hold (reductions add ~2 KB), at most 4 per CU, no more than the tasks
+    int grid(int lds, long tasks) const
+    {
+        const int per_cu = std::max(1, std::min(4, lds_cu / (lds + 2048)));
+        return (int)std::max(1L, std::min((long)per_cu * cus, tasks));
+    }
     std::vector<Class> cls;
     void *arena = nullptr;
     BRun *d_runs = nullptr;
@@ -238,6 +272,7 @@ kg_status setup(Batch &b, const kg_run_desc *runs, int nruns, const std::vector<
         R.E_final = std::nan("");
         const size_t q = up((size_t)d.n * d.n * R.P * 16);
         const size_t s = up((size_t)d.n * R.ntx * d.n * R.W * 16);
+        b.bytes.push_back(q + 2 * s);
         qoff[r] = off;
         off += q;
         s0off[r] = off;
@@ -260,7 +295,7 @@ kg_status setup(Batch &b, const kg_run_desc *runs, int nruns, const std::vector<
     }
     // per class: task lists (run-major), partial offsets relative to the class
     std::vector<size_t> o_xt(b.cls.size()), o_yt(b.cls.size()), o_cnt(b.cls.size()),
-        o_list(b.cls.size()), o_pa(b.cls.size()), o_pc(b.cls.size());
+        o_list(b.cls.size()), o_pa(b.cls.size()), o_pc(b.cls.size()), o_ccnt(b.cls.size());
     for (size_t k = 0; k < b.cls.size(); ++k) {
         Class &c = b.cls[k];
         for (size_t q = 0; q < c.runs.size(); ++q) {
@@ -286,6 +321,8 @@ kg_status setup(Batch &b, const kg_run_desc *runs, int nruns, const std::vector<
         off += up(2 * sizeof(double) * c.xfull.size());
         o_pc[k] = off;
         off += up(2 * sizeof(double) * c.yfull.size());
+        o_ccnt[k] = off;
+        off += up(2 * sizeof(int) * c.runs.size());
     }
     const size_t o_runs = off;
     off += up(sizeof(BRun) * nruns);
@@ -299,10 +336,10 @@ kg_status setup(Batch &b, const kg_run_desc *runs, int nruns, const std::vector<
         b.host[r].tw = base + tw_off[b.host[r].n];
     }
     b.d_runs = (BRun *)(base + o_runs);
-    int cus = 256, dev = 0, lds_cu = 160 * 1024;
+    int dev = 0;
     (void)hipGetDevice(&dev);
-    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    (void)hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev);
+    (void)hipDeviceGetAttribute(&b.cus, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipDeviceGetAttribute(&b.lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev);
     for (size_t k = 0; k < b.cls.size(); ++k) {
         Class &c = b.cls[k];
         c.d_xt = (BTask *)(base + o_xt[k]);
@@ -311,15 +348,10 @@ kg_status setup(Batch &b, const kg_run_desc *runs, int nruns, const std::vector<
         c.d_list = (int *)(base + o_list[k]);
         c.d_pa = (double *)(base + o_pa[k]);
         c.d_pc = (double *)(base + o_pc[k]);
+        c.d_ccnt = (int *)(base + o_ccnt[k]);
         c.nlist = (int)c.runs.size();
-        // persistent grids: as many 256-thread workgroups as the LDS lets a CU
-        // hold (reductions add ~2 KB), at most 4 per CU, no more than the tasks
-        auto grid = [&](int lds, long tasks) {
-            const int per_cu = std::max(1, std::min(4, lds_cu / (lds + 2048)));
-            return (int)std::max(1L, std::min((long)per_cu * cus, tasks));
-        };
-        c.gx = grid(c.L->x_lds, (long)c.xfull.size());
-        c.gyz = grid(c.L->yz_lds, (long)c.yfull.size());
+        c.gx = b.grid(c.L->x_lds, (long)c.xfull.size());
+        c.gyz = b.grid(c.L->yz_lds, (long)c.yfull.size());
         const int cnt[2] = {(int)c.xfull.size(), (int)c.yfull.size()};
         BCHK(hipMemcpyAsync(c.d_xt, c.xfull.data(), sizeof(BTask) * c.xfull.size(), hipMemcpyHostToDevice, b.st));
         BCHK(hipMemcpyAsync(c.d_yt, c.yfull.data(), sizeof(BTask) * c.yfull.size(), hipMemcpyHostToDevice, b.st));
@@ -344,19 +376,20 @@ kg_status setup(Batch &b, const kg_run_desc *runs, int nruns, const std::vector<
     return KG_OK;
 }
 
-void launch_fin(Batch &b, const Class &c, hipStream_t st, int mode, int want)
+void launch_fin(Batch &b, const View &v, hipStream_t st, int mode, int want)
 {
-    const int g = std::max(1, std::min(c.nlist, 1024));
-    hipLaunchKernelGGL(kb_finalize, dim3(g), dim3(256), 0, st, b.d_runs, c.d_list, c.nlist, c.d_pa,
-                       c.d_pc, mode, want);
+    const int g = std::max(1, std::min(v.nlist, 1024));
+    hipLaunchKernelGGL(kb_finalize, dim3(g), dim3(256), 0, st, b.d_runs, v.list, v.nlist, v.fa, v.fc,
+                       mode, want);
 }
 
 // Initial levels, energy of the initial pair and the first working field.
 kg_status init(Batch &b)
 {
     hipStream_t st = b.st;
-    for (const Class &c : b.cls) {
-        const Launch &L = *c.L;
+    for (const Class &cl : b.cls) {
+        const Launch &L = *cl.L;
+        const View c = cl.whole();
         L.x(c, st, b.d_runs, X_GAUSS, 0, 1);  // N^0 = F[u0^3] -> S1
         L.y(c, st, b.d_runs, -1, 0);
         L.z(c, st, b.d_runs, Z_FWD_STATE, 0, 1);
@@ -376,15 +409,20 @@ kg_status init(Batch &b)
     return KG_OK;
 }
 
-void enqueue_steps(Batch &b, const Class &c, hipStream_t st, int nsteps)
+// nsteps steps of a class, chunk by chunk: a chunk's fields stay in the
+// memory-side cache across its steps (runs are independent, so the order of
+// steps across chunks is free).
+void enqueue_steps(Batch &b, const Class &cl, hipStream_t st, int nsteps)
 {
-    const Launch &L = *c.L;
-    for (int i = 0; i < nsteps; ++i) {
-        L.x(c, st, b.d_runs, X_STEP, 0, 0);
-        L.y(c, st, b.d_runs, -1, 0);
-        L.z(c, st, b.d_runs, Z_STEP, 0, 0);
-        L.y(c, st, b.d_runs, 1, 0);
-        launch_fin(b, c, st, BF_STEP, 0);
+    const Launch &L = *cl.L;
+    for (const View &c : cl.chunks) {
+        for (int i = 0; i < nsteps; ++i) {
+            L.x(c, st, b.d_runs, X_STEP, 0, 0);
+            L.y(c, st, b.d_runs, -1, 0);
+            L.z(c, st, b.d_runs, Z_STEP, 0, 0);
+            L.y(c, st, b.d_runs, 1, 0);
+            launch_fin(b, c, st, BF_STEP, 0);
+        }
     }
 }
 
@@ -438,6 +476,29 @@ kg_status compact(Batch &b, int want, int &nsel)
         nsel += (int)list.size();
         // the finalize grid reads nlist; the full list stays allocated
         c.nlist = (int)list.size();
+        c.gx = b.grid(c.L->x_lds, (long)xt.size());
+        c.gyz = b.grid(c.L->yz_lds, (long)yt.size());
+        // chunks of consecutive runs of about chunk_bytes() of fields each
+        std::vector<int> ccnt;
+        c.chunks.clear();
+        const double cap = chunk_bytes();
+        for (size_t a = 0; a < list.size();) {
+            size_t e = a + 1;
+            double acc = (double)b.bytes[list[a]];
+            while (e < list.size() && cap > 0 && acc + b.bytes[list[e]] <= cap) acc += b.bytes[list[e++]];
+            if (cap <= 0) e = list.size();
+            const BRun &A = b.host[list[a]], &Z = b.host[list[e - 1]];
+            const int xa = A.xoff, xb = Z.xoff + Z.nxt, ya = A.zoff, yb = Z.zoff + Z.nzt;
+            const int k = (int)c.chunks.size();
+            ccnt.push_back(xb - xa);
+            ccnt.push_back(yb - ya);
+            c.chunks.push_back(View{BList{c.d_xt + xa, c.d_ccnt + 2 * k}, BList{c.d_yt + ya, c.d_ccnt + 2 * k + 1},
+                                    c.d_pa + 2 * xa, c.d_pc + 2 * ya, c.d_pa, c.d_pc, c.d_list + a,
+                                    (int)(e - a), b.grid(c.L->x_lds, xb - xa), b.grid(c.L->yz_lds, yb - ya)});
+            a = e;
+        }
+        if (!ccnt.empty())
+            BCHK(hipMemcpyAsync(c.d_ccnt, ccnt.data(), sizeof(int) * ccnt.size(), hipMemcpyHostToDevice, b.st));
         const int cnt[2] = {(int)xt.size(), (int)yt.size()};
         if (!xt.empty())
             BCHK(hipMemcpyAsync(c.d_xt, xt.data(), sizeof(BTask) * xt.size(), hipMemcpyHostToDevice, b.st));
@@ -516,8 +577,8 @@ kg_status run_batch(const kg_run_desc *runs, int nruns, const std::vector<int> &
     if (fin > 0) {
         for (const Class &c : b.cls) {
             if (c.nlist == 0) continue;
-            c.L->x(c, st, b.d_runs, X_REDUCE, 2, 0);
-            launch_fin(b, c, st, BF_FINAL, 2);
+            c.L->x(c.whole(), st, b.d_runs, X_REDUCE, 2, 0);
+            launch_fin(b, c.whole(), st, BF_FINAL, 2);
         }
         BCHK(hipGetLastError());
     }

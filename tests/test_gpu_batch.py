@@ -113,3 +113,24 @@ def test_batch_rejects_bad_descriptors(kg):
     with pytest.raises(kg.KGError) as e:
         kg.kg_batch_run([dict(n=32, A=1, sigma=(1, 0, 1), dt=0.01, max_steps=5, threshold=0)])
     assert e.value.status == kg.KG_E_INVALID
+
+
+def test_chunks_do_not_change_results(kg, monkeypatch):
+    """Each size class steps chunk by chunk (a graph replays all its steps on
+    one chunk before the next); runs are independent, so whole classes, the
+    default chunks and one run per chunk give bitwise the same results."""
+    runs = [dict(n=n, A=A, sigma=(1.0, 0.9, 1.2), dt=0.005, max_steps=300, threshold=1e3)
+            for n in (32, 48) for A in (0.6, 1.4, 3.5, 5.0, 6.5)]
+    out = {}
+    for mb in ("0", None, "1"):  # 1 MB: every run is a chunk of its own
+        if mb is None:
+            monkeypatch.delenv("KG_BATCH_CHUNK_MB", raising=False)
+        else:
+            monkeypatch.setenv("KG_BATCH_CHUNK_MB", mb)
+        out[mb], _ = kg.kg_batch_run(runs)
+    assert any(r["blew_up"] for r in out["0"]) and not all(r["blew_up"] for r in out["0"])
+    for mb in (None, "1"):
+        for a, b in zip(out["0"], out[mb]):
+            for k in ("blew_up", "steps_done", "t_blowup", "E0", "max_abs_u"):
+                assert a[k] == b[k], (mb, k)
+            assert (np.isnan(a["E_final"]) and np.isnan(b["E_final"])) or a["E_final"] == b["E_final"]
