@@ -156,8 +156,11 @@ def main():
         return dict(elapsed=elapsed, series=series, drift=abs(E_end - E0) / abs(E0), ms=ms,
                     kbytes=kbytes)
 
-    r64 = timed_run(kg.KG_FP64)
+    # FP32 first: each precision's workspace is then fresh device memory, as
+    # for a single solver in a new process (FP32 placed in the block freed by
+    # the FP64 solver measured about 2% slower; FP64 does not depend on it)
     r32 = timed_run(kg.KG_FP32)
+    r64 = timed_run(kg.KG_FP64)
     for m, e in r64["series"]:
         print(f"step {m:5d}  E^(m+1/2) = {e:.15e}", file=sys.stderr)
     elapsed, drift, ms = r64["elapsed"], r64["drift"], r64["ms"]
