@@ -251,3 +251,49 @@ def test_graph_replays_match_single_step_launches(kg):
             assert np.array_equal(a.u(), b.u())
             assert a.energy() == b.energy()
         assert np.array_equal(a.records(0, 48)[0], b.records(0, 48)[0])
+
+
+def test_stepping_after_a_blowup_and_argument_checks(kg):
+    """After a blow-up the counter stays at the blown level, further steps and
+    the energy report KG_BLOWUP; zero steps are a no-op, negative ones an
+    error."""
+    with kg.Solver(8, 0.01, blowup_threshold=1e3) as s:
+        s.set_state(ki.uniform(8, 1.5))
+        st, done = s.step(0)
+        assert st == kg.KG_OK and done == 0
+        with pytest.raises(kg.KGError) as e:
+            s.step(-1)
+        assert e.value.status == kg.KG_E_INVALID
+        st, done = s.step(200)
+        assert st == kg.KG_BLOWUP and done == 145
+        st, done = s.step(20)  # graphs and single steps alike do nothing now
+        assert st == kg.KG_BLOWUP and done == 145
+        assert s.stats() == (145, True, 145)
+        assert np.isnan(s.energy()[0])
+
+
+def test_disabled_threshold_still_stops_at_nonfinite_values(kg):
+    """threshold <= 0 disables the max|u| test, but a level with a non-finite
+    value still ends the run, at the oracle's level."""
+    dt = 0.01
+    ref = oracle.run(ki.uniform(8, 1.5), dt, 300, threshold=0.0)
+    assert ref["blowup_step"] > 145
+    with kg.Solver(8, dt, blowup_threshold=0.0) as s:
+        s.set_state(ki.uniform(8, 1.5))
+        st, done = s.step(300)
+    assert st == kg.KG_BLOWUP and done == ref["blowup_step"]
+
+
+def test_records_keep_the_last_65536_levels(kg):
+    n, steps = 8, 65536 + 40
+    with kg.Solver(n, 0.01, linear_only=True) as s:
+        s.set_state(ki.gaussian(n, 0.1))
+        st, done = s.step(steps)
+        assert st == kg.KG_OK and done == steps
+        elin, q4, maxu = s.records(40, 65536)
+        assert np.all(np.isfinite(elin)) and np.all(maxu > 0)
+        # eq. (2) conserves the linear energy exactly; rounding over 65 576 steps
+        assert np.abs(elin - elin[0]).max() <= 1e-9 * abs(elin[0])
+        with pytest.raises(kg.KGError) as e:
+            s.records(39, 1)
+        assert e.value.status == kg.KG_E_INVALID
