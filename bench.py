@@ -10,7 +10,7 @@ field is resident in HBM before timing starts.
 Prints one JSON line.  Also reports the dominant kernel's roofline figures
 (its algorithmic bytes over its average launch time, measured with HIP
 events inside the timed steps) and the CPU oracle timed on a bounded sample
-(one 512^3 step) on this host.
+(three 512^3 steps) on this host.
 """
 import argparse
 import json
@@ -102,15 +102,16 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def cpu_baseline(u0, dt):
-    """The oracle on this host: one step of the same workload (set-up excluded)."""
+def cpu_baseline(u0, dt, steps=3):
+    """The oracle on this host: a few steps of the same workload (set-up
+    excluded; about 12 s at 512^3 on 16 threads)."""
     import oracle
-    r = oracle.run(u0, dt, 1)
+    r = oracle.run(u0, dt, steps)
     secs = r["loop_seconds"]
-    return {"value": 1.0 / secs if secs > 0 else None, "unit": "steps/s",
+    return {"value": steps / secs if secs > 0 else None, "unit": "steps/s",
             "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"1 time step of the {u0.shape[0]}^3 FP64 workload (set-up excluded), "
-                      f"{secs:.2f} s"}
+            "sample": f"{steps} time steps of the {u0.shape[0]}^3 FP64 workload (set-up "
+                      f"excluded), {secs:.2f} s"}
 
 
 def main():
