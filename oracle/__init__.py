@@ -37,9 +37,12 @@ class Oracle:
                                   [ctypes.c_int, ctypes.c_int, dp, dp, ctypes.c_int, dp, dp])
         lib.kgo_first_step_modes.argtypes = ([ctypes.c_int] * 3 + [ctypes.c_double] * 4 +
                                              [ctypes.c_int, dp, ctypes.c_int, ip, dp, dp])
+        lib.kgo_run_c.argtypes = ([ctypes.c_int] * 3 + [ctypes.c_double] * 4 +
+                                  [ctypes.c_int, ctypes.c_double, ctypes.c_int, dp, dp,
+                                   ctypes.c_int, dp, dp, dp, dp, dp, ip])
         lib.kgo_num_threads.argtypes = []
         for f in (lib.kgo_fft1d, lib.kgo_fft3d, lib.kgo_fft3d_axis, lib.kgo_run, lib.kgo_state,
-                  lib.kgo_first_step_modes, lib.kgo_num_threads):
+                  lib.kgo_first_step_modes, lib.kgo_num_threads, lib.kgo_run_c):
             f.restype = ctypes.c_int
         self.lib = lib
 
@@ -95,6 +98,30 @@ class Oracle:
                                 ctypes.byref(blow), ctypes.byref(secs)), "run")
         return dict(u=u, u_prev=up, energy=energy, maxu=maxu, q4=q4, blowup_step=blow.value,
                     loop_seconds=secs.value)
+
+    def run_complex(self, u0, dt, nsteps, L=(8 * np.pi,) * 3, linear_only=False, threshold=0.0,
+                    mode=INIT_VELOCITY, aux=None):
+        """``run`` for a complex field (nonlinear term |u|^2 u): ``u0``, ``aux``
+        and the returned ``u``, ``u_prev`` are complex; ``maxu`` = max|u|,
+        ``q4`` = h^3 sum |u|^4."""
+        u0 = np.ascontiguousarray(u0, dtype=np.complex128)
+        nz, ny, nx = u0.shape
+        if aux is not None:
+            aux = np.ascontiguousarray(aux, dtype=np.complex128)
+            assert aux.shape == u0.shape
+        u = np.empty_like(u0)
+        up = np.empty_like(u0)
+        energy = np.empty(nsteps + 1)
+        maxu = np.empty(nsteps + 1)
+        q4 = np.empty(nsteps + 1)
+        blow = ctypes.c_int(-1)
+        _check(self.lib.kgo_run_c(nx, ny, nz, L[0], L[1], L[2], dt, int(bool(linear_only)),
+                                  float(threshold), mode, _ptr(u0.view(np.float64)),
+                                  _ptr(None if aux is None else aux.view(np.float64)), nsteps,
+                                  _ptr(u.view(np.float64)), _ptr(up.view(np.float64)),
+                                  _ptr(energy), _ptr(maxu), _ptr(q4), ctypes.byref(blow)),
+               "run_complex")
+        return dict(u=u, u_prev=up, energy=energy, maxu=maxu, q4=q4, blowup_step=blow.value)
 
     def state(self, u0, dt, nsteps, L=(8 * np.pi,) * 3, linear_only=False, mode=INIT_VELOCITY,
               aux=None):
@@ -168,6 +195,10 @@ def fft3d_axis(x, axis, sign=-1):
 
 def run(*args, **kw):
     return default().run(*args, **kw)
+
+
+def run_complex(*args, **kw):
+    return default().run_complex(*args, **kw)
 
 
 def state(*args, **kw):

@@ -9,6 +9,8 @@
  * on a periodic box, stepped with the second-order semi-implicit scheme of
  * Sec. 1.1.2, eq. (2), where time stepping happens in Fourier space and the
  * cubic term is formed in physical space (Sec. 1.1.2, closing paragraph).
+ * kgo_run_c steps a complex field, for which the cubic term is |u|^2 u
+ * (Sec. 1); it reduces to kgo_run for real data.
  *
  * Only the test suite, the smoke check and the CPU-baseline leg of the
  * benchmark load this library.  It shares no code, header, table or helper
@@ -596,4 +598,176 @@ int kgo_first_step_modes(int nx, int ny, int nz, double Lx, double Ly, double Lz
     }
     free(ex); free(ey); free(ez);
     return KGO_OK;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Complex fields                                                             */
+/* ------------------------------------------------------------------------- */
+
+/*
+ * The benchmark code of the paper also allows a complex field (Sec. 1.1.2);
+ * the cubic term of eq. (1) is then |u|^2 u (Sec. 1), which reduces to u^3
+ * for real u.  Fields are complex [z][y][x] arrays, interleaved re/im.
+ */
+
+/* dst = F[src] for a complex field src. */
+static int forward_cplx(const grid_t *g, const cplx *src, cplx *dst)
+{
+    memcpy(dst, src, sizeof(cplx) * npts(g));
+    return fft3d_axis(g->nx, g->ny, g->nz, dst, 0, -1) ||
+           fft3d_axis(g->nx, g->ny, g->nz, dst, 1, -1) ||
+           fft3d_axis(g->nx, g->ny, g->nz, dst, 2, -1);
+}
+
+/* u = F^{-1}[v] / M, complex; statistics max|u|, h^3 sum |u|^4, non-finite. */
+static int physical_cplx(const grid_t *g, const cplx *v, cplx *u, fieldstats_t *st)
+{
+    size_t M = npts(g);
+    memcpy(u, v, sizeof(cplx) * M);
+    if (fft3d_axis(g->nx, g->ny, g->nz, u, 0, 1) || fft3d_axis(g->nx, g->ny, g->nz, u, 1, 1) ||
+        fft3d_axis(g->nx, g->ny, g->nz, u, 2, 1))
+        return KGO_ENOMEM;
+    double h3 = (g->Lx / g->nx) * (g->Ly / g->ny) * (g->Lz / g->nz);
+    double mx = 0.0, s4 = 0.0;
+    int bad = 0;
+#pragma omp parallel for schedule(static) reduction(max : mx) reduction(+ : s4) reduction(| : bad)
+    for (size_t i = 0; i < M; i++) {
+        cplx x = u[i] / (double)M;
+        u[i] = x;
+        double m2 = creal(x) * creal(x) + cimag(x) * cimag(x);
+        if (!isfinite(creal(x)) || !isfinite(cimag(x)))
+            bad |= 1;
+        if (sqrt(m2) > mx)
+            mx = sqrt(m2);
+        s4 += m2 * m2;
+    }
+    st->maxabs = mx;
+    st->q4 = h3 * s4;
+    st->nonfinite = bad;
+    return KGO_OK;
+}
+
+/* w = chi F[|u|^2 u]. */
+static int nonlinear_cplx(const grid_t *g, const cplx *u, cplx *w, cplx *tmp)
+{
+    size_t M = npts(g);
+#pragma omp parallel for schedule(static)
+    for (size_t i = 0; i < M; i++) {
+        double m2 = creal(u[i]) * creal(u[i]) + cimag(u[i]) * cimag(u[i]);
+        tmp[i] = g->chi * m2 * u[i];
+    }
+    return forward_cplx(g, tmp, w);
+}
+
+/*
+ * kgo_run for a complex field: u0 and aux (u_t(0) or u^{-1}, may be NULL in
+ * velocity mode) are complex; the nonlinear term is chi |u|^2 u; u_out and
+ * uprev_out receive complex fields; maxu[n] = max_j |u^n_j|,
+ * q4[n] = h^3 sum_j |u^n_j|^4 and the energy is that of kgo_run (the same
+ * expression with |.|, equal to it for real data).  Start rules as in
+ * init_levels, with |u0|^2 u0 for u0^3.
+ */
+int kgo_run_c(int nx, int ny, int nz, double Lx, double Ly, double Lz, double dt,
+              int linear_only, double threshold, int mode,
+              const double *u0, const double *aux, int nsteps,
+              double *u_out, double *uprev_out,
+              double *energy, double *maxu, double *q4, int *blowup_step)
+{
+    int rc = check_args(nx, ny, nz, Lx, Ly, Lz, dt, mode, u0, aux, nsteps);
+    if (rc != KGO_OK)
+        return rc;
+    grid_t g = {nx, ny, nz, Lx, Ly, Lz, dt, linear_only ? 0.0 : 1.0};
+    size_t M = npts(&g);
+    cplx *vp = (cplx *)malloc(sizeof(cplx) * M);
+    cplx *vc = (cplx *)malloc(sizeof(cplx) * M);
+    cplx *w = (cplx *)malloc(sizeof(cplx) * M);
+    cplx *u = (cplx *)malloc(sizeof(cplx) * M);
+    cplx *tmp = (cplx *)malloc(sizeof(cplx) * M);
+    int blown = -1;
+    fieldstats_t st;
+    if (!vp || !vc || !w || !u || !tmp) {
+        rc = KGO_ENOMEM;
+        goto done;
+    }
+    for (int n = 0; n <= nsteps; n++) {
+        if (maxu) maxu[n] = NAN;
+        if (q4) q4[n] = NAN;
+        if (energy) energy[n] = NAN;
+    }
+    /* initial levels */
+    if (forward_cplx(&g, (const cplx *)u0, vc)) {
+        rc = KGO_ENOMEM;
+        goto done;
+    }
+    if (mode == KGO_INIT_TWO_LEVEL) {
+        if (forward_cplx(&g, (const cplx *)aux, vp)) {
+            rc = KGO_ENOMEM;
+            goto done;
+        }
+    } else {
+        if (nonlinear_cplx(&g, (const cplx *)u0, w, tmp)) {
+            rc = KGO_ENOMEM;
+            goto done;
+        }
+        if (aux) {
+            if (forward_cplx(&g, (const cplx *)aux, vp)) {
+                rc = KGO_ENOMEM;
+                goto done;
+            }
+        } else {
+            memset(vp, 0, sizeof(cplx) * M);
+        }
+#pragma omp parallel for collapse(2) schedule(static)
+        for (int iz = 0; iz < nz; iz++)
+            for (int iy = 0; iy < ny; iy++)
+                for (int ix = 0; ix < nx; ix++) {
+                    size_t i = ((size_t)iz * ny + iy) * nx + ix;
+                    double al, be;
+                    scheme_coeffs(&g, ix, iy, iz, &al, &be);
+                    vp[i] = 0.5 * al * vc[i] - g.dt * vp[i] + 0.5 * be * w[i];
+                }
+    }
+    if ((rc = physical_cplx(&g, vp, u, &st)) != KGO_OK)
+        goto done;
+    double q4_prev = st.q4;
+    double elin_prev = linear_energy(&g, vp, vc);
+    for (int n = 0; n <= nsteps; n++) {
+        if ((rc = physical_cplx(&g, vc, u, &st)) != KGO_OK)
+            goto done;
+        if (maxu) maxu[n] = st.nonfinite ? NAN : st.maxabs;
+        if (q4) q4[n] = st.q4;
+        if (energy) energy[n] = elin_prev - g.chi * (q4_prev + st.q4) / 8.0;
+        int is_blown = st.nonfinite || (threshold > 0 && st.maxabs > threshold);
+        if (is_blown || n == nsteps) {
+            if (is_blown) blown = n;
+            if (u_out) memcpy(u_out, u, sizeof(cplx) * M);
+            break;
+        }
+        /* v^{n+1} = alpha v^n - v^{n-1} + beta chi F[|u^n|^2 u^n], over v^{n-1} */
+        if (nonlinear_cplx(&g, u, w, tmp)) {
+            rc = KGO_ENOMEM;
+            goto done;
+        }
+#pragma omp parallel for collapse(2) schedule(static)
+        for (int iz = 0; iz < nz; iz++)
+            for (int iy = 0; iy < ny; iy++)
+                for (int ix = 0; ix < nx; ix++) {
+                    size_t i = ((size_t)iz * ny + iy) * nx + ix;
+                    double al, be;
+                    scheme_coeffs(&g, ix, iy, iz, &al, &be);
+                    vp[i] = al * vc[i] - vp[i] + be * w[i];
+                }
+        elin_prev = linear_energy(&g, vc, vp);
+        q4_prev = st.q4;
+        cplx *t = vp; vp = vc; vc = t;
+    }
+    if (uprev_out) {
+        if ((rc = physical_cplx(&g, vp, tmp, &st)) != KGO_OK)
+            goto done;
+        memcpy(uprev_out, tmp, sizeof(cplx) * M);
+    }
+done:
+    if (blowup_step) *blowup_step = blown;
+    free(vp); free(vc); free(w); free(u); free(tmp);
+    return rc;
 }

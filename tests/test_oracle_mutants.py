@@ -11,6 +11,7 @@ import pytest
 import kg_inputs as ki
 import oracle
 from oracle.build import SRC, build_oracle
+from tests.test_oracle_complex import charge, coeffs, wave
 from tests.test_oracle_pins import (cd_solution, dense_laplacian, gaussian_energy,
                                     omega_of_mode)
 
@@ -43,6 +44,16 @@ MUTANTS = {
                               "energy[n] = elin_prev - g.chi * (q4_prev + st.q4) / 4.0;"),
     "energy_kinetic_dt": ("s += dd / (g->dt * g->dt) + w2 * pp / 4.0;", "s += dd / g->dt + w2 * pp / 4.0;"),
     "energy_level_mix": ("elin_prev = linear_energy(&g, vc, vp);", "elin_prev = linear_energy(&g, vc, vc);"),
+    # complex fields
+    "complex_u_cubed": ("tmp[i] = g->chi * m2 * u[i];", "tmp[i] = g->chi * u[i] * u[i] * u[i];"),
+    "complex_modulus_real_part": (
+        "double m2 = creal(u[i]) * creal(u[i]) + cimag(u[i]) * cimag(u[i]);",
+        "double m2 = creal(u[i]) * creal(u[i]);"),
+    "complex_imag_dropped": ("cplx x = u[i] / (double)M;", "cplx x = creal(u[i]) / (double)M;"),
+    "complex_inverse_sign": ("fft3d_axis(g->nx, g->ny, g->nz, u, 0, 1)",
+                             "fft3d_axis(g->nx, g->ny, g->nz, u, 0, -1)"),
+    "complex_quartic_real_part": ("s4 += m2 * m2;",
+                                  "s4 += creal(x) * creal(x) * creal(x) * creal(x);"),
 }
 
 
@@ -116,6 +127,28 @@ def battery(o):
         drifts.append(np.abs(rr["energy"] - rr["energy"][0]).max() / abs(rr["energy"][0]))
     if not (drifts[0] < 1e-2 and 3.0 < drifts[0] / drifts[1] < 5.0):
         failed.append("nonlinear_energy")
+    # complex field: nonlinear plane wave (|u|^2 u keeps it), its energy in
+    # closed form, and the discrete charge
+    n, dt, cm, amp = 16, 0.01, (1, 2, -3), 0.8
+    al, be = coeffs(n, dt, cm)
+    th = np.arccos((al + be * amp * amp) / 2)
+    r = o.run_complex(wave(n, cm, 0.0, amp), dt, 40, mode=oracle.INIT_TWO_LEVEL,
+                      aux=wave(n, cm, th, amp))
+    if not np.abs(r["u"] - wave(n, cm, -40 * th, amp)).max() <= 1e-11:
+        failed.append("complex_plane_wave")
+    k = 2 * np.pi * np.asarray(cm, float) / L
+    w2 = 1.0 + np.sum(k * k)
+    e = L ** 3 * amp ** 2 / 2 * (4 * np.sin(th / 2) ** 2 / dt ** 2 + w2 * np.cos(th / 2) ** 2) \
+        - L ** 3 * amp ** 4 / 4
+    if not np.allclose(r["energy"], e, rtol=1e-12, atol=0):
+        failed.append("complex_energy")
+    z, y, x = ki.mesh(n, L)
+    u0 = ki.gaussian(n, 1.1, (1.0, 0.8, 1.2)) * np.exp(1j * 0.6 * (x - 0.5 * y + 0.3 * z))
+    r0 = o.run_complex(u0, dt, 0, aux=0.4j * u0)
+    r1 = o.run_complex(u0, dt, 30, aux=0.4j * u0)
+    c0, c1 = charge(n, dt, r0["u_prev"], r0["u"]), charge(n, dt, r1["u_prev"], r1["u"])
+    if not (abs(c0) > 1.0 and abs(c1 - c0) <= 1e-12 * abs(c0)):
+        failed.append("complex_charge")
     return failed
 
 
