@@ -20,6 +20,7 @@
  * Conventions.
  *   - Real fields are double arrays of n*n*n values in [z][y][x] order, x
  *     fastest; grid point j along an axis sits at x_j = -L/2 + j*L/n.
+ *     Complex fields (kg_params.complex_field) interleave (re, im) per point.
  *   - Forward transforms are unnormalised with exp(-2 pi i j k / n); spectra
  *     returned by kg_get_spectrum are the half spectrum kx = 0..n/2 of the
  *     full 3D DFT, complex (re, im) doubles in [kz][ky][kx] order with
@@ -62,6 +63,11 @@ typedef struct {
                                 v^n and v^n - v^{n-1} */
     int linear_only;         /* nonzero drops the cubic term (linear KG equation) */
     double blowup_threshold; /* max|u| above this is a blow-up; <= 0 disables the test */
+    int complex_field;       /* nonzero: u is complex and the cubic term is |u|^2 u (Sec. 1;
+                                the benchmark code of Sec. 1.1.2 allows complex u).  Fields
+                                are then interleaved (re, im) doubles, 2*n^3 per field,
+                                spectra are the full n*n*n spectrum, max|u| and Q4 use
+                                the modulus.  Same scheme, energy and precisions. */
 } kg_params;
 
 typedef struct kg_plan_s kg_plan_t;
@@ -129,7 +135,7 @@ kg_status kg_kernel_times(const kg_plan_t *plan, double ms[5], int *nsteps);
 /*
  * Energy of Sec. 1.1 of the newest level pair (v^{n-1}, v^n), n = steps done:
  *   E^{n-1/2} = (h^3/(2M)) sum_k [|v^n - v^{n-1}|^2/dt^2 + (1+|k|^2)|v^n + v^{n-1}|^2/4]
- *               - chi (Q4^{n-1} + Q4^n) / 8,   Q4^m = h^3 sum_j (u^m_j)^4,
+ *               - chi (Q4^{n-1} + Q4^n) / 8,   Q4^m = h^3 sum_j |u^m_j|^4,
  * (M = n^3, h = L/n, chi = 0 for the linear equation), at time t = (n - 1/2) dt.
  * Synchronises the stream.  E or t may be NULL.
  */
@@ -147,13 +153,14 @@ kg_status kg_records(kg_plan_t *plan, int first, int count, double *elin, double
 /* Steps done, blow-up flag and blown level (-1 if none).  Synchronises. */
 kg_status kg_stats(kg_plan_t *plan, int *steps_done, int *blown_up, int *blowup_step);
 
-/* u^n (n = steps done) in physical space, n^3 doubles.  Off the hot path. */
+/* u^n (n = steps done) in physical space, n^3 doubles (2*n^3 interleaved
+ * re, im for a complex field).  Off the hot path. */
 kg_status kg_get_u(kg_plan_t *plan, double *u_out, int on_device);
 
 /*
  * Spectrum of a stored level: which = 0 gives v^n, which = 1 gives v^{n-1}
  * (n = steps done), as the half spectrum described above (n*n*(n/2+1)
- * complex values, 2 doubles each).
+ * complex values, 2 doubles each; the full n*n*n spectrum for a complex field).
  */
 kg_status kg_get_spectrum(kg_plan_t *plan, int which, double *out, int on_device);
 

@@ -77,7 +77,7 @@ bool layout(const kg_params *p, Layout &lo)
 {
     if (!p || !size_ok(p->n) || (p->precision != KG_FP64 && p->precision != KG_FP32)) return false;
     lo.n = p->n;
-    lo.H = p->n / 2 + 1;
+    lo.H = p->complex_field ? p->n : p->n / 2 + 1;  // full spectrum of a complex field
     lo.W = tile_width(p->precision);
     lo.ntx = (lo.H + lo.W - 1) / lo.W;
     lo.esz = p->precision == KG_FP32 ? 8 : 16;
@@ -86,7 +86,7 @@ bool layout(const kg_params *p, Layout &lo)
     lo.P = ((lo.ntx * lo.W + per_line - 1) / per_line) * per_line;
     lo.PZ = (long)lo.n * lo.P + plane_pad_bytes() / (long)lo.esz;
     auto ops = make_ops(p->n, p->precision, lo.W);
-    lo.nA = ops->x_blocks();
+    lo.nA = ops->x_blocks(p->complex_field ? 1 : 0);
     lo.nC = ops->z_blocks(lo.ntx);
     if (lo.nC < PAIR_BLOCKS) lo.nC = PAIR_BLOCKS;
     lo.q = up((size_t)lo.n * lo.PZ * lo.esz);
@@ -152,7 +152,10 @@ kg_status hip_fail(kg_plan_s *pl, hipError_t e, const char *where)
 
 Plan &P(kg_plan_s *p) { return *p; }
 
-// Device copy of a real field given on the host or the device.
+// Doubles per field: n^3, or 2 n^3 interleaved (re, im) for a complex field.
+size_t field_doubles(const kg_plan_s *pl) { return (size_t)pl->n * pl->n * pl->n * (pl->cf ? 2 : 1); }
+
+// Device copy of a field given on the host or the device.
 struct DevField {
     double *d = nullptr;
     bool own = false;
@@ -169,7 +172,7 @@ kg_status to_device(kg_plan_s *pl, const double *src, int on_device, DevField &f
         f.d = const_cast<double *>(src);
         return KG_OK;
     }
-    const size_t bytes = (size_t)pl->n * pl->n * pl->n * sizeof(double);
+    const size_t bytes = field_doubles(pl) * sizeof(double);
     HIPCHK(pl, hipMalloc((void **)&f.d, bytes));
     f.own = true;
     HIPCHK(pl, hipMemcpyAsync(f.d, src, bytes, hipMemcpyHostToDevice, pl->stream));
@@ -333,6 +336,7 @@ kg_status kg_plan(const kg_params *p, void *d_workspace, size_t ws_bytes, void *
     if (!pl) return KG_E_NOMEM;
     pl->p = *p;
     pl->n = lo.n;
+    pl->cf = p->complex_field ? 1 : 0;
     pl->H = lo.H;
     pl->W = lo.W;
     pl->ntx = lo.ntx;
@@ -761,7 +765,7 @@ kg_status kg_get_u(kg_plan_t *plan, double *u_out, int on_device)
     const void *S, *Ssub;
     stored_level(p, c, 0, S, Ssub);
     if ((s = physical_q(plan, S, Ssub)) != KG_OK) return s;
-    const size_t bytes = (size_t)p.n * p.n * p.n * sizeof(double);
+    const size_t bytes = field_doubles(&p) * sizeof(double);
     double *d = u_out;
     if (!on_device) HIPCHK(plan, hipMalloc((void **)&d, bytes));
     p.ops->x(p, X_C2R, nullptr, d, 0.0);
@@ -807,7 +811,7 @@ kg_status kg_get_spectrum(kg_plan_t *plan, int which, double *out, int on_device
 // Saved state: header, both levels, control block and the newest record.
 struct SaveHeader {
     uint64_t magic;
-    int32_t n, precision, W, pad;
+    int32_t n, precision, W, cf;
     double dt, L;
     int64_t s_bytes;
 };
@@ -828,7 +832,7 @@ kg_status kg_save_state(kg_plan_t *plan, void *host_buf, size_t bytes)
     kg_status s = read_ctl(plan, c);
     if (s != KG_OK) return s;
     char *b = (char *)host_buf;
-    SaveHeader h{KG_MAGIC, p.n, p.p.precision, p.W, 0, p.p.dt, p.L, (int64_t)p.s_bytes};
+    SaveHeader h{KG_MAGIC, p.n, p.p.precision, p.W, p.cf, p.p.dt, p.L, (int64_t)p.s_bytes};
     std::memcpy(b, &h, sizeof h);
     b += sizeof h;
     HIPCHK(plan, hipMemcpy(b, p.S[0], p.s_bytes, hipMemcpyDeviceToHost));
@@ -852,7 +856,7 @@ kg_status kg_load_state(kg_plan_t *plan, const void *host_buf, size_t bytes)
     SaveHeader h;
     std::memcpy(&h, b, sizeof h);
     if (h.magic != KG_MAGIC || h.n != p.n || h.precision != p.p.precision || h.W != p.W ||
-        h.s_bytes != (int64_t)p.s_bytes)
+        h.cf != p.cf || h.s_bytes != (int64_t)p.s_bytes)
         return fail(plan, KG_E_INVALID, "saved state does not match this plan");
     b += sizeof h;
     HIPCHK(plan, hipMemcpy(p.S[0], b, p.s_bytes, hipMemcpyHostToDevice));
@@ -906,7 +910,7 @@ kg_status kg_debug_inverse(kg_plan_t *plan, const double *spec, double *u, int o
     if (s != KG_OK) return s;
     p.ops->z(p, Z_INV_Q, nullptr, nullptr, 1.0, 0);
     p.ops->y(p, 1, false);
-    const size_t bytes = (size_t)p.n * p.n * p.n * sizeof(double);
+    const size_t bytes = field_doubles(&p) * sizeof(double);
     double *d = u;
     if (!on_device) HIPCHK(plan, hipMalloc((void **)&d, bytes));
     p.ops->x(p, X_C2R, nullptr, d, 0.0);

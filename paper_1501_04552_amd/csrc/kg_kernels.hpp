@@ -136,6 +136,8 @@ struct XCfg {
     static constexpr int SH = sizeof(T) == 8 ? 3 : 0;
     static constexpr int RS = lslots<N, SH>();
     static constexpr long blocks() { return ((long)N * N / 2 + PPB - 1) / PPB; }
+    // complex fields: one line per row, PPB rows per workgroup
+    static constexpr long blocks_c() { return ((long)N * N + PPB - 1) / PPB; }
 };
 
 // One workgroup's share of the x pass: line pairs blk*PPB .. blk*PPB+PPB-1.
@@ -278,14 +280,109 @@ __device__ __forceinline__ void xbody(const XArgs<T> &a, long blk, cx<T> *rows, 
     if constexpr (MODE == X_STEP) block_max_sum<256>(mx, s4, part);
 }
 
+// The x pass of a complex field (Sec. 1: the cubic term is |u|^2 u).  Q
+// holds the full spectrum, kx = 0..N-1, and each row is one complex line,
+// transformed as it stands: no packing of two lines and no Hermitian split.
+// The partials are max|u| and sum |u|^4.  Inputs and outputs of X_R2C /
+// X_C2R are interleaved (re, im) doubles [z][y][x]; X_GAUSS has no complex
+// form.
 template <typename T, int N, int MODE>
+__device__ __forceinline__ void xbody_c(const XArgs<T> &a, long blk, cx<T> *rows, double *part)
+{
+    static_assert(MODE != X_GAUSS, "no complex Gaussian input");
+    using C = XCfg<T, N>;
+    constexpr int E = Radix<N>::E, TPL = C::TPL, PPB = C::PPB, RS = C::RS;
+    constexpr int XSY = (64 % TPL == 0) ? SYNC_WAVE : SYNC_BLOCK;
+    const int t = threadIdx.x % TPL, l = threadIdx.x / TPL;
+    const long ln = blk * PPB + l;  // row (z, y) = (ln / N, ln % N)
+    const bool act = ln < (long)N * N;
+    const long lc = act ? ln : 0;   // lanes past the last row read row 0, store nothing
+    cx<T> *r = rows + l * RS;
+    cx<T> *q = a.Q + (lc / N) * a.PZ + (lc % N) * a.P;
+    cx<T> v[E];
+    double mx = 0.0, s4 = 0.0;
+
+    if constexpr (MODE == X_R2C) {
+        const double *s = a.rin + 2 * lc * N;
+        const double *s2 = a.rin2 ? a.rin2 + 2 * lc * N : nullptr;
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+            const int m = t + j * TPL;
+            double re = act ? s[2 * m] : 0.0, im = act ? s[2 * m + 1] : 0.0;
+            if (s2 && act) {
+                re -= s2[2 * m];
+                im -= s2[2 * m + 1];
+            }
+            T xr = (T)re, xi = (T)im;
+            if (a.chi != (T)0) {
+                const T m2 = xr * xr + xi * xi;
+                xr *= m2;
+                xi *= m2;
+            }
+            v[j] = mk(xr, xi);
+        }
+    } else {
+        cx<T> ld[E];
+#pragma unroll
+        for (int j = 0; j < E; ++j) ld[j] = q[t + j * TPL];
+#pragma unroll
+        for (int j = 0; j < E; ++j) v[j] = act ? ld[j] : mk<T>(0, 0);
+        fft_line<T, N, 1, XSY, C::SH>(v, r, 1, t, a.tw, 1);
+        // v[j] = u[m], m = t + j*TPL
+        if constexpr (MODE == X_C2R) {
+            if (act) {
+                double *d = a.rout + 2 * ln * N;
+#pragma unroll
+                for (int j = 0; j < E; ++j) {
+                    const int m = t + j * TPL;
+                    d[2 * m] = (double)v[j].re;
+                    d[2 * m + 1] = (double)v[j].im;
+                }
+            }
+            return;
+        }
+        // max of |u|^2 (fmax drops NaNs; the sum restores them), then the root
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+            const double ur = (double)v[j].re, ui = (double)v[j].im;
+            if (act) {
+                const double m2 = fma(ur, ur, ui * ui);
+                mx = fmax(mx, m2);
+                s4 = fma(m2, m2, s4);
+            }
+        }
+        if (s4 != s4) mx = s4;
+        mx = sqrt(mx);
+        if constexpr (MODE == X_REDUCE) {
+            block_max_sum<256>(mx, s4, part);
+            return;
+        }
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+            const T m2 = v[j].re * v[j].re + v[j].im * v[j].im;
+            v[j] = scale(v[j], a.chi * m2);
+        }
+        stage_sync<XSY>();
+    }
+    fft_line<T, N, -1, XSY, C::SH>(v, r, 1, t, a.tw, 1);
+    if (act) {
+#pragma unroll
+        for (int j = 0; j < E; ++j) q[t + j * TPL] = v[j];
+    }
+    if constexpr (MODE == X_STEP) block_max_sum<256>(mx, s4, part);
+}
+
+template <typename T, int N, int MODE, bool CF = false>
 __global__ __launch_bounds__(256) void k_xpass(XArgs<T> a)
 {
     __shared__ cx<T> rows[XCfg<T, N>::PPB * XCfg<T, N>::RS];
     if constexpr (MODE == X_STEP || MODE == X_REDUCE) {
         if (a.ctl->flag) return;
     }
-    xbody<T, N, MODE>(a, blockIdx.x, rows, a.part + 2 * blockIdx.x);
+    if constexpr (CF)
+        xbody_c<T, N, MODE>(a, blockIdx.x, rows, a.part + 2 * blockIdx.x);
+    else
+        xbody<T, N, MODE>(a, blockIdx.x, rows, a.part + 2 * blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -384,7 +481,21 @@ struct ZArgs {
     double chi;
     double scale;     // 1/M for Z_STEP and Z_INV_STATE
     int has_vel;      // Z_START: Q holds F_xy[u_t0]
+    int cf;           // complex field: kx runs over 0..N-1 (signed wavenumbers), every
+                      // mode has energy weight 1
 };
+
+// Signed mode number of index k on an axis of N points.
+template <int N>
+__device__ __forceinline__ int mode_of(int k) { return k <= N / 2 ? k : k - N; }
+
+// Energy weight of column kx: the half spectrum of a real field stands for
+// the full one (kx and N - kx), except on the kx = 0 and kx = N/2 planes.
+template <int N>
+__device__ __forceinline__ double kx_weight(int kx, int cf)
+{
+    return (cf || kx == 0 || kx == N / 2) ? 1.0 : 2.0;
+}
 
 // alpha, beta of eq. (2) and omega^2 for mode numbers (mx, my, mz).
 __device__ __forceinline__ void coeffs(int mx, int my, int mz, double ks2, double dt, double &al,
@@ -420,14 +531,14 @@ __device__ __forceinline__ void zbody(const ZArgs<T> &a, long blk, cx<T> *lds, d
     if constexpr (MODE == Z_PAIR) {
         double esum = 0.0;
         if (act) {
-            const int my = ky <= N / 2 ? ky : ky - N;
-            const double wgt = (kx == 0 || kx == N / 2) ? 1.0 : 2.0;
+            const int my = ky <= N / 2 ? ky : ky - N, mxx = mode_of<N>(kx);
+            const double wgt = kx_weight<N>(kx, a.cf);
             const double idt2 = 1.0 / (a.dt * a.dt);
 #pragma unroll
             for (int j = 0; j < E; ++j) {
                 const int kz = t + j * TPL, mz = kz <= N / 2 ? kz : kz - N;
                 double al, be, w2;
-                coeffs(kx, my, mz, a.ks2, a.dt, al, be, w2);
+                coeffs(mxx, my, mz, a.ks2, a.dt, al, be, w2);
                 const long si = sbase + (long)kz * W;
                 const cx<T> a0 = a.Sp[si], a1 = a.Sc[si];
                 double dr, di, sr, sim;
@@ -474,14 +585,14 @@ __device__ __forceinline__ void zbody(const ZArgs<T> &a, long blk, cx<T> *lds, d
         }
         return;
     }
-    const int my = ky <= N / 2 ? ky : ky - N;
+    const int my = ky <= N / 2 ? ky : ky - N, mxx = mode_of<N>(kx);
     if constexpr (MODE == Z_START) {
         if (act) {
 #pragma unroll
             for (int j = 0; j < E; ++j) {
                 const int kz = t + j * TPL, mz = kz <= N / 2 ? kz : kz - N;
                 double al, be, w2;
-                coeffs(kx, my, mz, a.ks2, a.dt, al, be, w2);
+                coeffs(mxx, my, mz, a.ks2, a.dt, al, be, w2);
                 const long si = sbase + (long)kz * W;
                 const cx<T> vc = a.Sc[si];
                 const cx<T> nl = a.chi != 0.0 ? a.Sp[si] : zero;
@@ -504,7 +615,7 @@ __device__ __forceinline__ void zbody(const ZArgs<T> &a, long blk, cx<T> *lds, d
     }
     double esum = 0.0;
     if constexpr (MODE == Z_STEP) {
-        const double wgt = (kx == 0 || kx == N / 2) ? 1.0 : 2.0;
+        const double wgt = kx_weight<N>(kx, a.cf);
         const double idt2 = 1.0 / (a.dt * a.dt);
         // The state loads of a batch of ZB positions are issued before any is
         // used, unconditionally (the padding columns of the last tile are
@@ -529,7 +640,7 @@ __device__ __forceinline__ void zbody(const ZArgs<T> &a, long blk, cx<T> *lds, d
             const int j = h * ZB + i;
             const int kz = t + j * TPL, mz = kz <= N / 2 ? kz : kz - N;
             double al, be, w2;
-            coeffs(kx, my, mz, a.ks2, a.dt, al, be, w2);
+            coeffs(mxx, my, mz, a.ks2, a.dt, al, be, w2);
             const long si = sbase + (long)kz * W;
             const cx<T> vc = vcs[i], vp = vps[i];
             double nr, ni, dr, di;  // v^{n+1} and v^{n+1} - v^n in FP64
@@ -622,12 +733,13 @@ void k_zpass(ZArgs<T> a)
 
 // Linear energy partials of a pair of levels stored in the state layout:
 // sum w_k [|v1 - v0|^2/dt^2 + omega_k^2 |v1 + v0|^2 / 4] (w_k = 1 on the kx = 0
-// and kx = n/2 planes, 2 elsewhere: the half spectrum stands for the full one).
+// and kx = n/2 planes, 2 elsewhere: the half spectrum stands for the full one;
+// w_k = 1 throughout for a complex field, cf).
 // S0 = v^{-1}, S1 = v^0 for two levels; S0 = v^0, S1 = Delta^0 for the
 // increment form.
 template <typename T, int N, int W>
 __global__ __launch_bounds__(256) void k_pair_energy(const cx<T> *S0, const cx<T> *S1, double *part,
-                                                     int H, int ntx, double ks2, double dt)
+                                                     int H, int ntx, double ks2, double dt, int cf)
 {
     const long total = (long)N * ntx * N * W;
     double esum = 0.0;
@@ -641,8 +753,8 @@ __global__ __launch_bounds__(256) void k_pair_energy(const cx<T> *S0, const cx<T
         if (kx >= H) continue;
         const int my = ky <= N / 2 ? ky : ky - N, mz = kz <= N / 2 ? kz : kz - N;
         double al, be, w2;
-        coeffs(kx, my, mz, ks2, dt, al, be, w2);
-        const double wgt = (kx == 0 || kx == N / 2) ? 1.0 : 2.0;
+        coeffs(mode_of<N>(kx), my, mz, ks2, dt, al, be, w2);
+        const double wgt = kx_weight<N>(kx, cf);
         const cx<T> a0 = S0[i], a1 = S1[i];
         double dr, di, sr, si;
         if constexpr (increment_form<T>()) {

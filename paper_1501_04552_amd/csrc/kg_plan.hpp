@@ -20,6 +20,7 @@ struct Ops;
 struct kg_plan_s {
     kg_params p{};
     int n = 0, H = 0, W = 0, ntx = 0, P = 0;
+    int cf = 0;   // complex field: full spectrum (H = n), cubic term |u|^2 u
     long PZ = 0;  // plane pitch of Q in elements (n * P plus optional padding)
     int zslab = 0;  // z planes per slab of the y-inverse / x / y-forward chain
     double L = 0, h3 = 0, ks2 = 0, invM = 0, escale = 0, chi = 1;
@@ -69,7 +70,7 @@ struct Ops {
     virtual void state_to_spec(Plan &pl, const void *S, const void *Ssub, double *out) = 0;
     virtual void q_to_spec(Plan &pl, double *out) = 0;
     virtual void spec_to_q(Plan &pl, const double *in) = 0;
-    virtual long x_blocks() const = 0;
+    virtual long x_blocks(int cf) const = 0;
     virtual long z_blocks(int ntx) const = 0;
     virtual int slab_quantum() const = 0;  // slab sizes must be multiples of this
 };
@@ -83,7 +84,7 @@ struct OpsImpl final : Ops {
     using YC = YZCfg<N, W>;
     static long yz_grid(int ntx) { return (long)ntx * ((N + YC::B - 1) / YC::B); }
 
-    long x_blocks() const override { return XCfg<T, N>::blocks(); }
+    long x_blocks(int cf) const override { return cf ? XCfg<T, N>::blocks_c() : XCfg<T, N>::blocks(); }
     long z_blocks(int ntx) const override { return yz_grid(ntx); }
     int slab_quantum() const override
     {
@@ -105,14 +106,25 @@ struct OpsImpl final : Ops {
         a.P = pl.P;
         a.PZ = pl.PZ;
         a.chi = (T)chi;
-        long nb = XCfg<T, N>::blocks();
+        long nb = x_blocks(pl.cf);
         if (nz > 0 && nz < N && (mode == X_STEP || mode == X_REDUCE)) {
-            const long b0 = (long)z0 * (N / 2) / XCfg<T, N>::PPB;
-            nb = (long)nz * (N / 2) / XCfg<T, N>::PPB;
+            // lines per plane: N/2 pairs of a real field, N rows of a complex one
+            const long lpp = pl.cf ? N : N / 2;
+            const long b0 = (long)z0 * lpp / XCfg<T, N>::PPB;
+            nb = (long)nz * lpp / XCfg<T, N>::PPB;
             a.Q += (long)z0 * pl.PZ;
             a.part += 2 * b0;
         }
         dim3 g((unsigned)nb), b(256);
+        if (pl.cf) {
+            switch (mode) {
+            case X_STEP: hipLaunchKernelGGL((k_xpass<T, N, X_STEP, true>), g, b, 0, pl.stream, a); break;
+            case X_REDUCE: hipLaunchKernelGGL((k_xpass<T, N, X_REDUCE, true>), g, b, 0, pl.stream, a); break;
+            case X_R2C: hipLaunchKernelGGL((k_xpass<T, N, X_R2C, true>), g, b, 0, pl.stream, a); break;
+            case X_C2R: hipLaunchKernelGGL((k_xpass<T, N, X_C2R, true>), g, b, 0, pl.stream, a); break;
+            }
+            return;
+        }
         switch (mode) {
         case X_STEP: hipLaunchKernelGGL((k_xpass<T, N, X_STEP>), g, b, 0, pl.stream, a); break;
         case X_REDUCE: hipLaunchKernelGGL((k_xpass<T, N, X_REDUCE>), g, b, 0, pl.stream, a); break;
@@ -161,6 +173,7 @@ struct OpsImpl final : Ops {
         a.chi = pl.chi;
         a.scale = scale;
         a.has_vel = has_vel;
+        a.cf = pl.cf;
         dim3 g((unsigned)yz_grid(pl.ntx)), b(YC::NT);
         switch (mode) {
         case Z_STEP: hipLaunchKernelGGL((k_zpass<T, N, W, Z_STEP>), g, b, 0, pl.stream, a); break;
@@ -175,7 +188,7 @@ struct OpsImpl final : Ops {
     {
         hipLaunchKernelGGL((k_pair_energy<T, N, W>), dim3(PAIR_BLOCKS), dim3(256), 0, pl.stream,
                            (const cx<T> *)S0, (const cx<T> *)S1, pl.partC, pl.H, pl.ntx, pl.ks2,
-                           pl.p.dt);
+                           pl.p.dt, pl.cf);
     }
     void state_to_spec(Plan &pl, const void *S, const void *Ssub, double *out) override
     {

@@ -32,7 +32,7 @@ KERNELS = ("x_pass", "y_forward", "z_update", "y_inverse", "finalize")
 class kg_params(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int), ("L", ctypes.c_double), ("dt", ctypes.c_double),
                 ("precision", ctypes.c_int), ("linear_only", ctypes.c_int),
-                ("blowup_threshold", ctypes.c_double)]
+                ("blowup_threshold", ctypes.c_double), ("complex_field", ctypes.c_int)]
 
 
 class kg_run_desc(ctypes.Structure):
@@ -125,9 +125,10 @@ def _check(status, plan=None, allow=(KG_OK,)):
     return status
 
 
-def make_params(n, dt, L=0.0, precision=KG_FP64, linear_only=False, blowup_threshold=0.0):
+def make_params(n, dt, L=0.0, precision=KG_FP64, linear_only=False, blowup_threshold=0.0,
+                complex_field=False):
     return kg_params(int(n), float(L), float(dt), int(precision), int(bool(linear_only)),
-                     float(blowup_threshold))
+                     float(blowup_threshold), int(bool(complex_field)))
 
 
 def kg_workspace_bytes(params):
@@ -145,13 +146,14 @@ def kg_destroy(plan):
 
 
 def _buf(x):
-    """(pointer, on_device) of a numpy array or a torch tensor."""
+    """(pointer, on_device) of a numpy array or a torch tensor (float64, or
+    complex128 for complex fields: interleaved re, im)."""
     if x is None:
         return None, 0
     if isinstance(x, np.ndarray):
-        assert x.flags.c_contiguous and x.dtype == np.float64
+        assert x.flags.c_contiguous and x.dtype in (np.float64, np.complex128)
         return x.ctypes.data, 0
-    assert x.is_contiguous() and x.is_cuda
+    assert x.is_contiguous() and x.is_cuda and x.dtype in (torch.float64, torch.complex128)
     return x.data_ptr(), 1
 
 
@@ -190,18 +192,19 @@ def kg_stats(plan):
     return s.value, bool(b.value), bs.value
 
 
-def kg_get_u(plan, n, out=None):
+def kg_get_u(plan, n, out=None, complex_field=False):
     if out is None:
-        out = np.empty((n, n, n))
+        out = np.empty((n, n, n), np.complex128 if complex_field else np.float64)
     p, d = _buf(out)
     _check(_lib.kg_get_u(plan, p, d), plan)
     return out
 
 
-def kg_get_spectrum(plan, n, which=0, out=None):
-    """Half spectrum [kz][ky][kx<=n/2] of v^n (which=0) or v^{n-1} (which=1)."""
+def kg_get_spectrum(plan, n, which=0, out=None, complex_field=False):
+    """Half spectrum [kz][ky][kx<=n/2] of v^n (which=0) or v^{n-1} (which=1);
+    the full spectrum [kz][ky][kx] for a complex field."""
     if out is None:
-        out = np.empty((n, n, n // 2 + 1), np.complex128)
+        out = np.empty((n, n, n if complex_field else n // 2 + 1), np.complex128)
     _check(_lib.kg_get_spectrum(plan, which, out.ctypes.data, 0), plan)
     return out
 
@@ -223,15 +226,17 @@ def kg_load_state(plan, buf):
 
 def kg_debug_forward(plan, u):
     n = u.shape[0]
-    spec = np.empty((n, n, n // 2 + 1), np.complex128)
+    spec = np.empty((n, n, n if np.iscomplexobj(u) else n // 2 + 1), np.complex128)
     _check(_lib.kg_debug_forward(plan, u.ctypes.data, spec.ctypes.data, 0), plan)
     return spec
 
 
 def kg_debug_inverse(plan, spec):
+    """Inverse 3D transform (with 1/M) of a half spectrum, or of a full one
+    (complex field plans: last axis n) into a complex field."""
     n = spec.shape[0]
     spec = np.ascontiguousarray(spec, np.complex128)
-    u = np.empty((n, n, n))
+    u = np.empty((n, n, n), np.complex128 if spec.shape[2] == n else np.float64)
     _check(_lib.kg_debug_inverse(plan, spec.ctypes.data, u.ctypes.data, 0), plan)
     return u
 

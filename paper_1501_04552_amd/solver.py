@@ -1,4 +1,5 @@
 """A plan with its workspace held in a torch device tensor."""
+import numpy as np
 import torch
 
 from . import kg as _kg
@@ -8,14 +9,18 @@ class Solver:
     """One Klein-Gordon run on the current GPU: owns a plan and its workspace.
 
     Work goes to torch's current stream at construction time.  Initial data
-    may be numpy arrays (host) or contiguous float64 torch tensors on the GPU.
+    may be numpy arrays (host) or contiguous float64 torch tensors on the GPU
+    (complex128 for a complex field).
     """
 
     def __init__(self, n, dt, L=0.0, linear_only=False, blowup_threshold=0.0,
-                 precision=_kg.KG_FP64):
-        """precision: KG_FP64 (0) or KG_FP32 (1)."""
+                 precision=_kg.KG_FP64, complex_field=False):
+        """precision: KG_FP64 (0) or KG_FP32 (1).  complex_field: u is complex
+        and the cubic term is |u|^2 u."""
         self.n = n
-        self.params = _kg.make_params(n, dt, L, precision, linear_only, blowup_threshold)
+        self.complex_field = bool(complex_field)
+        self.params = _kg.make_params(n, dt, L, precision, linear_only, blowup_threshold,
+                                      complex_field)
         nbytes = _kg.kg_workspace_bytes(self.params)
         if nbytes == 0:
             raise _kg.KGError(_kg.KG_E_INVALID, f"unsupported parameters n={n}, dt={dt}")
@@ -43,6 +48,11 @@ class Solver:
         self.close()
 
     def set_state(self, u0, aux=None, mode=_kg.KG_INIT_VELOCITY):
+        want = (np.complex128, torch.complex128) if self.complex_field else (np.float64,
+                                                                             torch.float64)
+        for x in (u0, aux):
+            if x is not None and x.dtype not in want:
+                raise TypeError(f"initial data of dtype {x.dtype}; this run takes {want[0]}")
         _kg.kg_set_state(self.plan, u0, aux, mode)
 
     def step(self, nsteps, sync=True):
@@ -58,10 +68,10 @@ class Solver:
         return _kg.kg_stats(self.plan)
 
     def u(self, out=None):
-        return _kg.kg_get_u(self.plan, self.n, out)
+        return _kg.kg_get_u(self.plan, self.n, out, self.complex_field)
 
     def spectrum(self, which=0):
-        return _kg.kg_get_spectrum(self.plan, self.n, which)
+        return _kg.kg_get_spectrum(self.plan, self.n, which, complex_field=self.complex_field)
 
     def save(self):
         return _kg.kg_save_state(self.plan)
