@@ -10,7 +10,9 @@ field is resident in HBM before timing starts.
 Prints one JSON line.  Also reports the dominant kernel's roofline figures
 (its algorithmic bytes over its average launch time, measured with HIP
 events inside the timed steps) and the CPU oracle timed on a bounded sample
-(three 512^3 steps) on this host.
+(three 512^3 steps) on this host.  Secondary legs: the FP32 path, a complex
+field (u0 times the phase exp(i x / 2), cubic term |u|^2 u) in both
+precisions, and the batched parametric sweep.
 """
 import argparse
 import json
@@ -131,11 +133,16 @@ def main():
     u0 = ki.gaussian(n, args.amplitude)
     u0_dev = torch.from_numpy(u0).cuda()
 
-    def timed_run(precision):
+    def timed_run(precision, complex_field=False):
         """Warm up, time args.steps steps (graph replays), then an event-timed
         run of the same length for per-kernel durations."""
-        solver = kg.Solver(n, dt, blowup_threshold=1e3, precision=precision)
-        solver.set_state(u0_dev)
+        solver = kg.Solver(n, dt, blowup_threshold=1e3, precision=precision,
+                           complex_field=complex_field)
+        if complex_field:
+            x = torch.from_numpy(ki.axis(n)).cuda()
+            solver.set_state((u0_dev.to(torch.complex128) * torch.exp(0.5j * x)).contiguous())
+        else:
+            solver.set_state(u0_dev)
         E0, _ = solver.energy()
         solver.step(args.warmup, sync=True)
         torch.cuda.synchronize()
@@ -162,6 +169,19 @@ def main():
     # the FP64 solver measured about 2% slower; FP64 does not depend on it)
     r32 = timed_run(kg.KG_FP32)
     r64 = timed_run(kg.KG_FP64)
+    cplx = {}
+    for name, prec in (("fp32", kg.KG_FP32), ("fp64", kg.KG_FP64)):
+        torch.cuda.empty_cache()
+        rc = timed_run(prec, complex_field=True)
+        tc = rc["elapsed"] / args.steps
+        zc = rc["kbytes"][kg.KERNELS.index("z_update")] / (rc["ms"][2] * 1e-3) / 1e9
+        sweep_c = n ** 3 * (16 if prec == kg.KG_FP64 else 8)  # full spectrum, one pass
+        cplx[name] = {"steps_per_s": 1.0 / tc, "ms_per_step": 1e3 * tc,
+                      "kernels_ms": dict(zip(kg.KERNELS, rc["ms"])),
+                      "z_update_GBs": zc, "z_update_hbm_frac": zc / HBM_PEAK_GBS,
+                      "step_model_GBs": (11 if prec == kg.KG_FP64 else 12) * sweep_c / tc / 1e9,
+                      "energy_drift": rc["drift"]}
+    torch.cuda.empty_cache()
     for m, e in r64["series"]:
         print(f"step {m:5d}  E^(m+1/2) = {e:.15e}", file=sys.stderr)
     elapsed, drift, ms = r64["elapsed"], r64["drift"], r64["ms"]
@@ -237,6 +257,9 @@ def main():
         "copy_GBs": copy_gbs,
         "energy_drift": drift,
         "fp32": fp32,
+        "complex_field": dict(cplx, workload=f"KG {n}^3 complex u0 = {args.amplitude} "
+                                             "exp(-|x|^2) exp(i x/2), u_t0 = 0, |u|^2 u, "
+                                             f"dt={dt}; full spectrum per level"),
     }
     if not args.no_sweep:
         line["sweep"] = sweep(args, kg, ki, torch)
