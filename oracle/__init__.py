@@ -31,14 +31,15 @@ class Oracle:
         lib.kgo_fft3d.argtypes = [ctypes.c_int] * 3 + [dp, ctypes.c_int]
         lib.kgo_fft3d_axis.argtypes = [ctypes.c_int] * 3 + [dp, ctypes.c_int, ctypes.c_int]
         lib.kgo_run.argtypes = ([ctypes.c_int] * 3 + [ctypes.c_double] * 4 +
-                                [ctypes.c_int, ctypes.c_double, ctypes.c_int, dp, dp,
+                                [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int, dp, dp,
                                  ctypes.c_int, dp, dp, dp, dp, dp, ip, dp])
         lib.kgo_state.argtypes = ([ctypes.c_int] * 3 + [ctypes.c_double] * 4 +
-                                  [ctypes.c_int, ctypes.c_int, dp, dp, ctypes.c_int, dp, dp])
+                                  [ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp, ctypes.c_int,
+                                   dp, dp])
         lib.kgo_first_step_modes.argtypes = ([ctypes.c_int] * 3 + [ctypes.c_double] * 4 +
                                              [ctypes.c_int, dp, ctypes.c_int, ip, dp, dp])
         lib.kgo_run_c.argtypes = ([ctypes.c_int] * 3 + [ctypes.c_double] * 4 +
-                                  [ctypes.c_int, ctypes.c_double, ctypes.c_int, dp, dp,
+                                  [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int, dp, dp,
                                    ctypes.c_int, dp, dp, dp, dp, dp, ip])
         lib.kgo_num_threads.argtypes = []
         for f in (lib.kgo_fft1d, lib.kgo_fft3d, lib.kgo_fft3d_axis, lib.kgo_run, lib.kgo_state,
@@ -72,8 +73,9 @@ class Oracle:
         return a
 
     def run(self, u0, dt, nsteps, L=(8 * np.pi,) * 3, linear_only=False, threshold=0.0,
-            mode=INIT_VELOCITY, aux=None):
+            mode=INIT_VELOCITY, aux=None, dealias=False):
         """Step eq. (2) ``nsteps`` times from ``u0`` (and ``aux`` = u_t(0) or u^{-1}).
+        ``dealias`` truncates the nonlinear term by the 2/3 rule.
 
         Returns a dict with ``u`` (u^nsteps or the blown-up level), ``u_prev``,
         ``energy`` (E^{-1/2}, E^{1/2}, ...), ``maxu`` and ``q4`` per level,
@@ -93,14 +95,14 @@ class Oracle:
         blow = ctypes.c_int(-1)
         secs = ctypes.c_double(0.0)
         _check(self.lib.kgo_run(nx, ny, nz, L[0], L[1], L[2], dt, int(bool(linear_only)),
-                                float(threshold), mode, _ptr(u0), _ptr(aux), nsteps, _ptr(u),
+                                int(bool(dealias)), float(threshold), mode, _ptr(u0), _ptr(aux), nsteps, _ptr(u),
                                 _ptr(up), _ptr(energy), _ptr(maxu), _ptr(q4),
                                 ctypes.byref(blow), ctypes.byref(secs)), "run")
         return dict(u=u, u_prev=up, energy=energy, maxu=maxu, q4=q4, blowup_step=blow.value,
                     loop_seconds=secs.value)
 
     def run_complex(self, u0, dt, nsteps, L=(8 * np.pi,) * 3, linear_only=False, threshold=0.0,
-                    mode=INIT_VELOCITY, aux=None):
+                    mode=INIT_VELOCITY, aux=None, dealias=False):
         """``run`` for a complex field (nonlinear term |u|^2 u): ``u0``, ``aux``
         and the returned ``u``, ``u_prev`` are complex; ``maxu`` = max|u|,
         ``q4`` = h^3 sum |u|^4."""
@@ -116,7 +118,7 @@ class Oracle:
         q4 = np.empty(nsteps + 1)
         blow = ctypes.c_int(-1)
         _check(self.lib.kgo_run_c(nx, ny, nz, L[0], L[1], L[2], dt, int(bool(linear_only)),
-                                  float(threshold), mode, _ptr(u0.view(np.float64)),
+                                  int(bool(dealias)), float(threshold), mode, _ptr(u0.view(np.float64)),
                                   _ptr(None if aux is None else aux.view(np.float64)), nsteps,
                                   _ptr(u.view(np.float64)), _ptr(up.view(np.float64)),
                                   _ptr(energy), _ptr(maxu), _ptr(q4), ctypes.byref(blow)),
@@ -124,7 +126,7 @@ class Oracle:
         return dict(u=u, u_prev=up, energy=energy, maxu=maxu, q4=q4, blowup_step=blow.value)
 
     def state(self, u0, dt, nsteps, L=(8 * np.pi,) * 3, linear_only=False, mode=INIT_VELOCITY,
-              aux=None):
+              aux=None, dealias=False):
         """Full complex spectra (v^{nsteps-1}, v^nsteps) after ``nsteps`` steps."""
         u0 = np.ascontiguousarray(u0, dtype=np.float64)
         nz, ny, nx = u0.shape
@@ -133,7 +135,7 @@ class Oracle:
         vp = np.empty(u0.shape, np.complex128)
         vc = np.empty(u0.shape, np.complex128)
         _check(self.lib.kgo_state(nx, ny, nz, L[0], L[1], L[2], dt, int(bool(linear_only)),
-                                  mode, _ptr(u0), _ptr(aux), nsteps, _ptr(vp.view(np.float64)),
+                                  int(bool(dealias)), mode, _ptr(u0), _ptr(aux), nsteps, _ptr(vp.view(np.float64)),
                                   _ptr(vc.view(np.float64))), "state")
         return vp, vc
 

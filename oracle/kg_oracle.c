@@ -209,10 +209,37 @@ typedef struct {
     double Lx, Ly, Lz;
     double dt;
     double chi; /* 1 with the cubic term, 0 for the linear equation */
+    int dealias; /* nonzero: 2/3-rule truncation of the nonlinear term */
 } grid_t;
 
 /* Signed integer wavenumber of mode index i on an axis of n points. */
 static int mode_number(int i, int n) { return i <= n / 2 ? i : i - n; }
+
+/*
+ * Optional dealiasing, an addition to the paper's plain pseudo-spectral
+ * method (which has none): the 2/3 rule applied to the nonlinear term.  A
+ * mode is kept when its wavenumber satisfies |m| <= n/3 (integer division)
+ * on every axis; the transformed nonlinear term is zeroed on all other modes
+ * before the update, so those evolve under the linear part of eq. (2) only.
+ */
+static int kept_mode(const grid_t *g, int ix, int iy, int iz)
+{
+    return abs(mode_number(ix, g->nx)) <= g->nx / 3 && abs(mode_number(iy, g->ny)) <= g->ny / 3 &&
+           abs(mode_number(iz, g->nz)) <= g->nz / 3;
+}
+
+static void truncate_nonlinear(const grid_t *g, cplx *w)
+{
+    if (!g->dealias)
+        return;
+    int nx = g->nx, ny = g->ny, nz = g->nz;
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int iz = 0; iz < nz; iz++)
+        for (int iy = 0; iy < ny; iy++)
+            for (int ix = 0; ix < nx; ix++)
+                if (!kept_mode(g, ix, iy, iz))
+                    w[((size_t)iz * ny + iy) * nx + ix] = 0.0;
+}
 
 /* omega_k^2 = 1 + |k|^2: the Fourier symbol of (1 - Lap). */
 static double omega2(const grid_t *g, int ix, int iy, int iz)
@@ -338,6 +365,7 @@ static int init_levels(const grid_t *g, int mode, const double *u0, const double
         cube[i] = g->chi * u0[i] * u0[i] * u0[i];
     if (forward_real(g, cube, w))
         return KGO_ENOMEM;
+    truncate_nonlinear(g, w);
     if (aux) {
         if (forward_real(g, aux, vp))
             return KGO_ENOMEM;
@@ -370,6 +398,7 @@ static int advance(const grid_t *g, cplx *vp, const cplx *vc, cplx *w, double *c
         cube[i] = g->chi * cube[i] * cube[i] * cube[i];
     if (forward_real(g, cube, w))
         return KGO_ENOMEM;
+    truncate_nonlinear(g, w);
     int nx = g->nx, ny = g->ny, nz = g->nz;
 #pragma omp parallel for collapse(2) schedule(static)
     for (int iz = 0; iz < nz; iz++)
@@ -409,6 +438,7 @@ static int check_args(int nx, int ny, int nz, double Lx, double Ly, double Lz, d
  *   *loop_seconds = wall time of the steps themselves (levels 0..nsteps-1:
  *                  inverse transform, cubic term, forward transform, update),
  *                  without the set-up and the last level's transform.
+ * dealias nonzero truncates the nonlinear term by the 2/3 rule (kept_mode).
  * Any output pointer may be NULL.  Entries after a blow-up stay NaN.
  */
 static double wall_seconds(void)
@@ -419,7 +449,7 @@ static double wall_seconds(void)
 }
 
 int kgo_run(int nx, int ny, int nz, double Lx, double Ly, double Lz, double dt,
-            int linear_only, double threshold, int mode,
+            int linear_only, int dealias, double threshold, int mode,
             const double *u0, const double *aux, int nsteps,
             double *u_out, double *uprev_out,
             double *energy, double *maxu, double *q4, int *blowup_step,
@@ -429,7 +459,7 @@ int kgo_run(int nx, int ny, int nz, double Lx, double Ly, double Lz, double dt,
     if (rc != KGO_OK)
         return rc;
 
-    grid_t g = {nx, ny, nz, Lx, Ly, Lz, dt, linear_only ? 0.0 : 1.0};
+    grid_t g = {nx, ny, nz, Lx, Ly, Lz, dt, linear_only ? 0.0 : 1.0, dealias != 0};
     size_t M = npts(&g);
     cplx *vp = (cplx *)malloc(sizeof(cplx) * M);   /* v^{n-1} */
     cplx *vc = (cplx *)malloc(sizeof(cplx) * M);   /* v^n     */
@@ -494,13 +524,13 @@ done:
  * re/im in [z][y][x] order.
  */
 int kgo_state(int nx, int ny, int nz, double Lx, double Ly, double Lz, double dt,
-              int linear_only, int mode, const double *u0, const double *aux, int nsteps,
-              double *v_prev, double *v_cur)
+              int linear_only, int dealias, int mode, const double *u0, const double *aux,
+              int nsteps, double *v_prev, double *v_cur)
 {
     int rc = check_args(nx, ny, nz, Lx, Ly, Lz, dt, mode, u0, aux, nsteps);
     if (rc != KGO_OK || !v_prev || !v_cur)
         return rc != KGO_OK ? rc : KGO_EINVAL;
-    grid_t g = {nx, ny, nz, Lx, Ly, Lz, dt, linear_only ? 0.0 : 1.0};
+    grid_t g = {nx, ny, nz, Lx, Ly, Lz, dt, linear_only ? 0.0 : 1.0, dealias != 0};
     size_t M = npts(&g);
     cplx *vp = (cplx *)malloc(sizeof(cplx) * M);
     cplx *vc = (cplx *)malloc(sizeof(cplx) * M);
@@ -656,7 +686,10 @@ static int nonlinear_cplx(const grid_t *g, const cplx *u, cplx *w, cplx *tmp)
         double m2 = creal(u[i]) * creal(u[i]) + cimag(u[i]) * cimag(u[i]);
         tmp[i] = g->chi * m2 * u[i];
     }
-    return forward_cplx(g, tmp, w);
+    if (forward_cplx(g, tmp, w))
+        return KGO_ENOMEM;
+    truncate_nonlinear(g, w);
+    return KGO_OK;
 }
 
 /*
@@ -668,7 +701,7 @@ static int nonlinear_cplx(const grid_t *g, const cplx *u, cplx *w, cplx *tmp)
  * init_levels, with |u0|^2 u0 for u0^3.
  */
 int kgo_run_c(int nx, int ny, int nz, double Lx, double Ly, double Lz, double dt,
-              int linear_only, double threshold, int mode,
+              int linear_only, int dealias, double threshold, int mode,
               const double *u0, const double *aux, int nsteps,
               double *u_out, double *uprev_out,
               double *energy, double *maxu, double *q4, int *blowup_step)
@@ -676,7 +709,7 @@ int kgo_run_c(int nx, int ny, int nz, double Lx, double Ly, double Lz, double dt
     int rc = check_args(nx, ny, nz, Lx, Ly, Lz, dt, mode, u0, aux, nsteps);
     if (rc != KGO_OK)
         return rc;
-    grid_t g = {nx, ny, nz, Lx, Ly, Lz, dt, linear_only ? 0.0 : 1.0};
+    grid_t g = {nx, ny, nz, Lx, Ly, Lz, dt, linear_only ? 0.0 : 1.0, dealias != 0};
     size_t M = npts(&g);
     cplx *vp = (cplx *)malloc(sizeof(cplx) * M);
     cplx *vc = (cplx *)malloc(sizeof(cplx) * M);

@@ -12,6 +12,7 @@ import kg_inputs as ki
 import oracle
 from oracle.build import SRC, build_oracle
 from tests.test_oracle_complex import charge, coeffs, wave
+from tests.test_oracle_dealias import betas, kept_box
 from tests.test_oracle_pins import (cd_solution, dense_laplacian, gaussian_energy,
                                     omega_of_mode)
 
@@ -54,6 +55,19 @@ MUTANTS = {
                              "fft3d_axis(g->nx, g->ny, g->nz, u, 0, -1)"),
     "complex_quartic_real_part": ("s4 += m2 * m2;",
                                   "s4 += creal(x) * creal(x) * creal(x) * creal(x);"),
+    # dealiasing
+    "dealias_cutoff_strict": ("abs(mode_number(ix, g->nx)) <= g->nx / 3",
+                              "abs(mode_number(ix, g->nx)) < g->nx / 3"),
+    "dealias_axis_mix": ("abs(mode_number(iy, g->ny)) <= g->ny / 3",
+                         "abs(mode_number(iy, g->ny)) <= g->nx / 3"),
+    "dealias_skipped_in_steps": (
+        "cube[i] = g->chi * cube[i] * cube[i] * cube[i];\n    if (forward_real(g, cube, w))\n"
+        "        return KGO_ENOMEM;\n    truncate_nonlinear(g, w);",
+        "cube[i] = g->chi * cube[i] * cube[i] * cube[i];\n    if (forward_real(g, cube, w))\n"
+        "        return KGO_ENOMEM;"),
+    "dealias_skipped_complex": ("    if (forward_cplx(g, tmp, w))\n        return KGO_ENOMEM;\n"
+                                "    truncate_nonlinear(g, w);",
+                                "    if (forward_cplx(g, tmp, w))\n        return KGO_ENOMEM;"),
 }
 
 
@@ -149,6 +163,34 @@ def battery(o):
     c0, c1 = charge(n, dt, r0["u_prev"], r0["u"]), charge(n, dt, r1["u_prev"], r1["u"])
     if not (abs(c0) > 1.0 and abs(c1 - c0) <= 1e-12 * abs(c0)):
         failed.append("complex_charge")
+    # dealiasing: one step differs from the plain one by beta F[u0^3] exactly
+    # on the removed modes; band-limited data stays in the box; a complex
+    # plane wave outside the box advances linearly
+    shape, Ls, dt = (12, 16, 24), (L, 0.8 * L, 0.6 * L), 0.02
+    u0 = 0.8 * rng.standard_normal(shape)
+    um1 = u0 + 0.01 * rng.standard_normal(shape)
+    _, plain = o.state(u0, dt, 1, L=Ls, mode=oracle.INIT_TWO_LEVEL, aux=um1)
+    _, dal = o.state(u0, dt, 1, L=Ls, mode=oracle.INIT_TWO_LEVEL, aux=um1, dealias=True)
+    keep = kept_box(shape)
+    exp = betas(shape, Ls, dt) * np.fft.fftn(u0 ** 3)
+    if not (np.array_equal(plain[keep], dal[keep]) and
+            np.abs((plain - dal)[~keep] - exp[~keep]).max() <= 1e-12 * np.abs(exp).max()):
+        failed.append("dealias_one_step")
+    n = 24
+    spec = np.fft.fftn(rng.standard_normal((n, n, n)))
+    spec[~kept_box((n, n, n))] = 0.0
+    ub = np.real(np.fft.ifftn(spec))
+    ub *= 1.5 / np.abs(ub).max()
+    _, v = o.state(ub, 0.01, 20, dealias=True)
+    if not np.abs(v[~kept_box((n, n, n))]).max() <= 1e-12 * np.abs(v).max():
+        failed.append("dealias_band_limited")
+    cm, amp = (9, 0, 1), 0.8
+    al, be = coeffs(n, 0.01, cm)
+    th = np.arccos(al / 2)
+    r = o.run_complex(wave(n, cm, 0.0, amp), 0.01, 40, mode=oracle.INIT_TWO_LEVEL,
+                      aux=wave(n, cm, th, amp), dealias=True)
+    if not np.abs(r["u"] - wave(n, cm, -40 * th, amp)).max() <= 1e-11:
+        failed.append("dealias_complex_wave")
     return failed
 
 
