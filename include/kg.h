@@ -68,6 +68,11 @@ typedef struct {
                                 are then interleaved (re, im) doubles, 2*n^3 per field,
                                 spectra are the full n*n*n spectrum, max|u| and Q4 use
                                 the modulus.  Same scheme, energy and precisions. */
+    int dealias;             /* nonzero: 2/3-rule dealiasing (not in the paper, whose
+                                pseudo-spectral scheme has none): the transformed nonlinear
+                                term is zeroed on every mode with |m| > n/3 (integer
+                                division) on some axis before the update of eq. (2), so
+                                those modes evolve under the linear part alone */
 } kg_params;
 
 typedef struct kg_plan_s kg_plan_t;

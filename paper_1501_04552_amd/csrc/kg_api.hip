@@ -337,6 +337,7 @@ kg_status kg_plan(const kg_params *p, void *d_workspace, size_t ws_bytes, void *
     pl->p = *p;
     pl->n = lo.n;
     pl->cf = p->complex_field ? 1 : 0;
+    pl->dkc = p->dealias ? p->n / 3 : 0;
     pl->H = lo.H;
     pl->W = lo.W;
     pl->ntx = lo.ntx;

@@ -19,6 +19,23 @@
 
 namespace kg {
 
+// Rounding of the transforms.  Every kernel inlines its own copy of these
+// routines, and a compiler free to fuse a product into a following add picks
+// the fusions per kernel, so two kernels could round the same transform
+// differently.  The routines below therefore switch contraction off and
+// write their fused multiply-adds explicitly: a transform rounds the same
+// way in every kernel that runs it.  (The resting field that a step's z pass
+// leaves and the one rebuilt from a stored level by another kernel must
+// agree bit for bit for a checkpoint to resume bitwise.)
+template <typename T>
+__device__ __forceinline__ T fmx(T a, T b, T c)
+{
+    if constexpr (sizeof(T) == 4)
+        return __builtin_fmaf(a, b, c);
+    else
+        return __builtin_fma(a, b, c);
+}
+
 template <typename T>
 struct alignas(2 * sizeof(T)) cx {
     T re, im;
@@ -33,24 +50,38 @@ __device__ __forceinline__ cx<T> mk(T a, T b)
     return r;
 }
 template <typename T>
-__device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return mk(a.re + b.re, a.im + b.im); }
+__device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b)
+{
+#pragma clang fp contract(off)
+    return mk(a.re + b.re, a.im + b.im);
+}
 template <typename T>
-__device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return mk(a.re - b.re, a.im - b.im); }
+__device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b)
+{
+#pragma clang fp contract(off)
+    return mk(a.re - b.re, a.im - b.im);
+}
 template <typename T>
 __device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b)
 {
-    return mk(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re);
+#pragma clang fp contract(off)
+    return mk(fmx(a.re, b.re, -(a.im * b.im)), fmx(a.re, b.im, a.im * b.re));
 }
 // a * conj(b)
 template <typename T>
 __device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> b)
 {
-    return mk(a.re * b.re + a.im * b.im, a.im * b.re - a.re * b.im);
+#pragma clang fp contract(off)
+    return mk(fmx(a.re, b.re, a.im * b.im), fmx(a.im, b.re, -(a.re * b.im)));
 }
 template <typename T>
 __device__ __forceinline__ cx<T> conjg(cx<T> a) { return mk(a.re, -a.im); }
 template <typename T>
-__device__ __forceinline__ cx<T> scale(cx<T> a, T s) { return mk(a.re * s, a.im * s); }
+__device__ __forceinline__ cx<T> scale(cx<T> a, T s)
+{
+#pragma clang fp contract(off)
+    return mk(a.re * s, a.im * s);
+}
 
 // Streaming global accesses (each value is read or written once per pass):
 // nontemporal hints keep them from displacing reused data in the caches.
@@ -85,6 +116,7 @@ __device__ __forceinline__ cx<T> rot90(cx<T> a)
 template <int R, int DIR, typename T>
 __device__ __forceinline__ void dft(cx<T> (&x)[R])
 {
+#pragma clang fp contract(off)
     if constexpr (R == 2) {
         cx<T> a = x[0], b = x[1];
         x[0] = a + b;
@@ -93,11 +125,11 @@ __device__ __forceinline__ void dft(cx<T> (&x)[R])
         // w_3 = -1/2 + DIR i sqrt(3)/2
         const T h = (T)0.86602540378443864676372317075293618347;
         const cx<T> t1 = x[1] + x[2];
-        const cx<T> t2 = x[0] - scale(t1, (T)0.5);
-        const cx<T> t3 = scale(rot90<DIR>(x[1] - x[2]), h);
+        const cx<T> t2 = mk(fmx(t1.re, (T)-0.5, x[0].re), fmx(t1.im, (T)-0.5, x[0].im));
+        const cx<T> d = rot90<DIR>(x[1] - x[2]);
         x[0] = x[0] + t1;
-        x[1] = t2 + t3;
-        x[2] = t2 - t3;
+        x[1] = mk(fmx(d.re, h, t2.re), fmx(d.im, h, t2.im));
+        x[2] = mk(fmx(d.re, -h, t2.re), fmx(d.im, -h, t2.im));
     } else if constexpr (R == 4) {
         cx<T> y0 = x[0] + x[2], y1 = x[0] - x[2];
         cx<T> y2 = x[1] + x[3], y3 = rot90<DIR>(x[1] - x[3]);
@@ -197,6 +229,7 @@ __device__ __forceinline__ void stage_sync()
 template <int R, typename T>
 __device__ __forceinline__ void twiddles(cx<T> (&w)[R], const cx<T> *__restrict__ tw, int idx)
 {
+#pragma clang fp contract(off)
     w[1] = tw[idx];
     if constexpr (R == 3) w[2] = tw[2 * idx];
     if constexpr (R >= 4) {
@@ -220,6 +253,7 @@ template <typename T, int NL, int DIR, int SY = SYNC_BLOCK, int SH = 3, int S = 
 __device__ __forceinline__ void fft_line(cx<T> (&v)[Radix<NL>::E], cx<T> *lds, int ls, int t,
                                          const cx<T> *__restrict__ tw, int twm)
 {
+#pragma clang fp contract(off)
     using P = Radix<NL>;
     constexpr int E = P::E, TPL = P::TPL;
     constexpr int R = P::radix(S), L = P::lbefore(S);

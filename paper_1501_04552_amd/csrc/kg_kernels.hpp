@@ -483,11 +483,18 @@ struct ZArgs {
     int has_vel;      // Z_START: Q holds F_xy[u_t0]
     int cf;           // complex field: kx runs over 0..N-1 (signed wavenumbers), every
                       // mode has energy weight 1
+    int dkc;          // > 0: 2/3-rule dealiasing, the nonlinear term keeps the modes with
+                      // |m| <= dkc (= N/3) on every axis; 0: no truncation
 };
 
 // Signed mode number of index k on an axis of N points.
 template <int N>
 __device__ __forceinline__ int mode_of(int k) { return k <= N / 2 ? k : k - N; }
+
+// Largest |m| of the modes the nonlinear term keeps: dkc when dealiasing,
+// else N (every mode).
+template <int N>
+__device__ __forceinline__ int keep_cut(int dkc) { return dkc > 0 ? dkc : N; }
 
 // Energy weight of column kx: the half spectrum of a real field stands for
 // the full one (kx and N - kx), except on the kx = 0 and kx = N/2 planes.
@@ -586,6 +593,9 @@ __device__ __forceinline__ void zbody(const ZArgs<T> &a, long blk, cx<T> *lds, d
         return;
     }
     const int my = ky <= N / 2 ? ky : ky - N, mxx = mode_of<N>(kx);
+    // dealiasing: the (x, y) part of the kept-mode test, per lane
+    const int kcut = keep_cut<N>(a.dkc);
+    const bool keep_xy = abs(mxx) <= kcut && abs(my) <= kcut;
     if constexpr (MODE == Z_START) {
         if (act) {
 #pragma unroll
@@ -595,7 +605,7 @@ __device__ __forceinline__ void zbody(const ZArgs<T> &a, long blk, cx<T> *lds, d
                 coeffs(mxx, my, mz, a.ks2, a.dt, al, be, w2);
                 const long si = sbase + (long)kz * W;
                 const cx<T> vc = a.Sc[si];
-                const cx<T> nl = a.chi != 0.0 ? a.Sp[si] : zero;
+                const cx<T> nl = a.chi != 0.0 && keep_xy && abs(mz) <= kcut ? a.Sp[si] : zero;
                 double re, im;
                 if constexpr (increment_form<T>()) {
                     // Delta^0 = v^0 - v^{-1} = (2a/(1+a)) v^0 + dt F[u_t0] - (beta/2) chi N^0
@@ -622,9 +632,10 @@ __device__ __forceinline__ void zbody(const ZArgs<T> &a, long blk, cx<T> *lds, d
         // allocated), so they are in flight together; loads under a
         // per-position branch would each wait for their own data before the
         // next is issued.  FP64 batches 4 positions to stay within 128 VGPRs
-        // (1, 2 and 8 measured slower at 512^3); FP32 takes 8.
+        // (1, 2 and 8 measured slower at 512^3); FP32 takes 8, or 6 for the
+        // 12 positions of 3 * 2^a sizes (12 at once spill registers).
         constexpr int ZB0 = sizeof(T) == 8 ? 4 : 8;
-        constexpr int ZB = E % ZB0 == 0 ? ZB0 : E;  // batches cover all E positions
+        constexpr int ZB = E % ZB0 == 0 ? ZB0 : E % 6 == 0 && ZB0 >= 6 ? 6 : E % 4 == 0 ? 4 : E;
         static_assert(E % ZB == 0, "state-load batches must tile the positions");
 #pragma unroll
         for (int h = 0; h < E / ZB; ++h) {
@@ -643,17 +654,18 @@ __device__ __forceinline__ void zbody(const ZArgs<T> &a, long blk, cx<T> *lds, d
             coeffs(mxx, my, mz, a.ks2, a.dt, al, be, w2);
             const long si = sbase + (long)kz * W;
             const cx<T> vc = vcs[i], vp = vps[i];
+            const cx<T> nl = keep_xy && abs(mz) <= kcut ? v[j] : zero;
             double nr, ni, dr, di;  // v^{n+1} and v^{n+1} - v^n in FP64
             if constexpr (increment_form<T>()) {
                 // Delta^{n+1} = Delta^n - (2 - alpha) v^n + beta N^n
                 const double c2 = 2.0 - al;
-                dr = (double)vp.re - c2 * (double)vc.re + be * (double)v[j].re;
-                di = (double)vp.im - c2 * (double)vc.im + be * (double)v[j].im;
+                dr = (double)vp.re - c2 * (double)vc.re + be * (double)nl.re;
+                di = (double)vp.im - c2 * (double)vc.im + be * (double)nl.im;
                 nr = (double)vc.re + dr;
                 ni = (double)vc.im + di;
             } else {
-                nr = al * (double)vc.re - (double)vp.re + be * (double)v[j].re;
-                ni = al * (double)vc.im - (double)vp.im + be * (double)v[j].im;
+                nr = al * (double)vc.re - (double)vp.re + be * (double)nl.re;
+                ni = al * (double)vc.im - (double)vp.im + be * (double)nl.im;
                 dr = nr - (double)vc.re;
                 di = ni - (double)vc.im;
             }

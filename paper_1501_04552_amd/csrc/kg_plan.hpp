@@ -21,6 +21,7 @@ struct kg_plan_s {
     kg_params p{};
     int n = 0, H = 0, W = 0, ntx = 0, P = 0;
     int cf = 0;   // complex field: full spectrum (H = n), cubic term |u|^2 u
+    int dkc = 0;  // dealiasing cut-off n/3 of the nonlinear term, 0 when off
     long PZ = 0;  // plane pitch of Q in elements (n * P plus optional padding)
     int zslab = 0;  // z planes per slab of the y-inverse / x / y-forward chain
     double L = 0, h3 = 0, ks2 = 0, invM = 0, escale = 0, chi = 1;
@@ -174,6 +175,7 @@ struct OpsImpl final : Ops {
         a.scale = scale;
         a.has_vel = has_vel;
         a.cf = pl.cf;
+        a.dkc = pl.dkc;
         dim3 g((unsigned)yz_grid(pl.ntx)), b(YC::NT);
         switch (mode) {
         case Z_STEP: hipLaunchKernelGGL((k_zpass<T, N, W, Z_STEP>), g, b, 0, pl.stream, a); break;

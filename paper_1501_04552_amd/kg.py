@@ -32,7 +32,8 @@ KERNELS = ("x_pass", "y_forward", "z_update", "y_inverse", "finalize")
 class kg_params(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int), ("L", ctypes.c_double), ("dt", ctypes.c_double),
                 ("precision", ctypes.c_int), ("linear_only", ctypes.c_int),
-                ("blowup_threshold", ctypes.c_double), ("complex_field", ctypes.c_int)]
+                ("blowup_threshold", ctypes.c_double), ("complex_field", ctypes.c_int),
+                ("dealias", ctypes.c_int)]
 
 
 class kg_run_desc(ctypes.Structure):
@@ -126,9 +127,9 @@ def _check(status, plan=None, allow=(KG_OK,)):
 
 
 def make_params(n, dt, L=0.0, precision=KG_FP64, linear_only=False, blowup_threshold=0.0,
-                complex_field=False):
+                complex_field=False, dealias=False):
     return kg_params(int(n), float(L), float(dt), int(precision), int(bool(linear_only)),
-                     float(blowup_threshold), int(bool(complex_field)))
+                     float(blowup_threshold), int(bool(complex_field)), int(bool(dealias)))
 
 
 def kg_workspace_bytes(params):

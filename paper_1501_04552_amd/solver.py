@@ -14,13 +14,14 @@ class Solver:
     """
 
     def __init__(self, n, dt, L=0.0, linear_only=False, blowup_threshold=0.0,
-                 precision=_kg.KG_FP64, complex_field=False):
+                 precision=_kg.KG_FP64, complex_field=False, dealias=False):
         """precision: KG_FP64 (0) or KG_FP32 (1).  complex_field: u is complex
-        and the cubic term is |u|^2 u."""
+        and the cubic term is |u|^2 u.  dealias: 2/3-rule truncation of the
+        nonlinear term."""
         self.n = n
         self.complex_field = bool(complex_field)
         self.params = _kg.make_params(n, dt, L, precision, linear_only, blowup_threshold,
-                                      complex_field)
+                                      complex_field, dealias)
         nbytes = _kg.kg_workspace_bytes(self.params)
         if nbytes == 0:
             raise _kg.KGError(_kg.KG_E_INVALID, f"unsupported parameters n={n}, dt={dt}")

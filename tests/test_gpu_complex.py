@@ -182,21 +182,22 @@ def test_blowup_step_matches_oracle(kg):
     assert bstep == ref["blowup_step"] == done
 
 
-def test_save_load_and_plan_mismatch(kg):
+@pytest.mark.parametrize("precision", [0, 1])
+def test_save_load_and_plan_mismatch(kg, precision):
     n, dt = 24, 0.01
     u0 = phased_gaussian(n, 1.2, (1.0, 0.9, 1.1), (0.5, 0.2, -0.3))
-    with kg.Solver(n, dt, complex_field=True) as s:
+    with kg.Solver(n, dt, precision=precision, complex_field=True) as s:
         s.set_state(u0)
         s.step(10)
         buf = s.save()
         s.step(15)
         ua = s.u()
-    with kg.Solver(n, dt, complex_field=True) as s:
+    with kg.Solver(n, dt, precision=precision, complex_field=True) as s:
         s.load(buf)
         s.step(15)
         ub = s.u()
     assert np.array_equal(ua, ub)
-    with kg.Solver(n, dt) as s:  # a real-field plan refuses a complex state
+    with kg.Solver(n, dt, precision=precision) as s:  # a real-field plan refuses a complex state
         with pytest.raises(kg.KGError):
             s.load(buf)
     with kg.Solver(n, dt, complex_field=True) as s:
