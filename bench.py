@@ -39,6 +39,9 @@ def parse():
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--sweep-runs", type=int, default=512)
     ap.add_argument("--sweep-seq-sample", type=int, default=16)
+    ap.add_argument("--complex", choices=("on", "off", "only"), default="on",
+                    help="complex-field legs: with the real ones (on), none (off), or alone "
+                         "(only: one JSON line for the complex FP64 leg, for profiling)")
     return ap.parse_args()
 
 
@@ -164,24 +167,42 @@ def main():
         return dict(elapsed=elapsed, series=series, drift=abs(E_end - E0) / abs(E0), ms=ms,
                     kbytes=kbytes)
 
+    def complex_legs():
+        out = {}
+        for name, prec in (("fp32", kg.KG_FP32), ("fp64", kg.KG_FP64)):
+            torch.cuda.empty_cache()
+            out[name] = complex_leg(prec)
+        torch.cuda.empty_cache()
+        return dict(out, workload=f"KG {n}^3 complex u0 = {args.amplitude} exp(-|x|^2) "
+                                  f"exp(i x/2), u_t0 = 0, |u|^2 u, dt={dt}; full spectrum per level")
+
+    def complex_leg(prec):
+        rc = timed_run(prec, complex_field=True)
+        tc = rc["elapsed"] / args.steps
+        zc = rc["kbytes"][kg.KERNELS.index("z_update")] / (rc["ms"][2] * 1e-3) / 1e9
+        sweep_c = n ** 3 * (16 if prec == kg.KG_FP64 else 8)  # full spectrum, one pass
+        return {"steps_per_s": 1.0 / tc, "ms_per_step": 1e3 * tc,
+                "kernels_ms": dict(zip(kg.KERNELS, rc["ms"])),
+                "z_update_GBs": zc, "z_update_hbm_frac": zc / HBM_PEAK_GBS,
+                "step_model_GBs": (11 if prec == kg.KG_FP64 else 12) * sweep_c / tc / 1e9,
+                "energy_drift": rc["drift"]}
+
+    if args.complex == "only":
+        c = complex_legs()
+        print(json.dumps({"metric": f"{n}^3 complex-field time steps/s (FP64)",
+                          "value": c["fp64"]["steps_per_s"], "unit": "steps/s", "n_gpus": 1,
+                          "steps": args.steps, "warmup": args.warmup,
+                          "ms_per_step": c["fp64"]["ms_per_step"], "higher_is_better": True,
+                          "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+                          "data": "synthetic", "config": {"workload": c["workload"]},
+                          "complex_field": c}), flush=True)
+        return
     # FP32 first: each precision's workspace is then fresh device memory, as
     # for a single solver in a new process (FP32 placed in the block freed by
     # the FP64 solver measured about 2% slower; FP64 does not depend on it)
     r32 = timed_run(kg.KG_FP32)
     r64 = timed_run(kg.KG_FP64)
-    cplx = {}
-    for name, prec in (("fp32", kg.KG_FP32), ("fp64", kg.KG_FP64)):
-        torch.cuda.empty_cache()
-        rc = timed_run(prec, complex_field=True)
-        tc = rc["elapsed"] / args.steps
-        zc = rc["kbytes"][kg.KERNELS.index("z_update")] / (rc["ms"][2] * 1e-3) / 1e9
-        sweep_c = n ** 3 * (16 if prec == kg.KG_FP64 else 8)  # full spectrum, one pass
-        cplx[name] = {"steps_per_s": 1.0 / tc, "ms_per_step": 1e3 * tc,
-                      "kernels_ms": dict(zip(kg.KERNELS, rc["ms"])),
-                      "z_update_GBs": zc, "z_update_hbm_frac": zc / HBM_PEAK_GBS,
-                      "step_model_GBs": (11 if prec == kg.KG_FP64 else 12) * sweep_c / tc / 1e9,
-                      "energy_drift": rc["drift"]}
-    torch.cuda.empty_cache()
+    cplx = complex_legs() if args.complex == "on" else None
     for m, e in r64["series"]:
         print(f"step {m:5d}  E^(m+1/2) = {e:.15e}", file=sys.stderr)
     elapsed, drift, ms = r64["elapsed"], r64["drift"], r64["ms"]
@@ -257,10 +278,9 @@ def main():
         "copy_GBs": copy_gbs,
         "energy_drift": drift,
         "fp32": fp32,
-        "complex_field": dict(cplx, workload=f"KG {n}^3 complex u0 = {args.amplitude} "
-                                             "exp(-|x|^2) exp(i x/2), u_t0 = 0, |u|^2 u, "
-                                             f"dt={dt}; full spectrum per level"),
     }
+    if cplx:
+        line["complex_field"] = cplx
     if not args.no_sweep:
         line["sweep"] = sweep(args, kg, ki, torch)
     if not args.no_cpu_baseline and n <= 512:
