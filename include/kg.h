@@ -14,6 +14,10 @@
  * The conserved energy of Sec. 1.1 is evaluated in double precision as a
  * correctness and fault check.
  *
+ * Options (kg_params): FP32 transforms (precision), the linear equation
+ * (linear_only), complex fields with the cubic term |u|^2 u (complex_field),
+ * and 2/3-rule dealiasing of the nonlinear term (dealias).
+ *
  * Every step runs in the library's own HIP kernels on one GPU: no vendor
  * FFT.  Work is enqueued on the stream given to kg_plan.
  *
@@ -109,7 +113,9 @@ void kg_destroy(kg_plan_t *plan);
  *   mode KG_INIT_VELOCITY: u0 = u(0), aux = u_t(0) (NULL means zero).  The
  *     second level eq. (2) needs is the symmetric start
  *     v^{-1} = (alpha/2) v^0 - dt F[u_t(0)] + (beta/2) F[u0^3],
- *     so that (v^1 - v^{-1})/(2 dt) = F[u_t(0)] (the paper leaves the start open).
+ *     so that (v^1 - v^{-1})/(2 dt) = F[u_t(0)] (the paper leaves the start open);
+ *     |u0|^2 u0 for a complex field, truncated like every nonlinear term when
+ *     dealiasing.
  *   mode KG_INIT_TWO_LEVEL: u0 = u^0, aux = u^{-1} (required).
  * Inputs are copied; they may be released after the call returns.
  * Also evaluates the energy of the initial pair (see kg_energy).

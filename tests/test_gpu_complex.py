@@ -224,3 +224,61 @@ def test_slab_chain_is_bitwise_independent_of_slab_count(kg, monkeypatch):
             out.append((s.u(), s.energy()[0]))
     assert np.array_equal(out[0][0], out[1][0])
     assert out[0][1] == out[1][1]
+
+
+def device_wave(torch, n, mode, phase, amp):
+    """amp exp(i (k.x + phase)) on the grid, built on the GPU, [z][y][x]."""
+    x = torch.tensor(ki.axis(n), device="cuda", dtype=torch.float64)
+    k = [2 * np.pi * m / L for m in mode]
+    ph = (k[2] * x)[:, None, None] + (k[1] * x)[None, :, None] + (k[0] * x)[None, None, :]
+    return (amp * torch.exp(1j * (ph + phase))).contiguous()
+
+
+@pytest.mark.parametrize("precision,dealias,mode,tol", [
+    (0, False, (3, -2, 5), 1e-11),       # nonlinear frequency, FP64
+    (1, False, (3, -2, 5), 2e-5),        # FP32 storage of the same wave
+    (0, True, (171, 4, -2), 1e-11),      # outside the kept box: linear frequency
+    (0, True, (170, -170, 9), 1e-11)])   # on the box edge (512 // 3 = 170): nonlinear
+def test_plane_wave_at_512(kg, precision, dealias, mode, tol):
+    """The benchmark's grid and launch configuration (slab chain on two
+    streams, graph replays): a complex plane wave advances by exactly theta
+    per step."""
+    import torch
+    n, dt, steps, amp = 512, 0.005, 24, 0.8
+    al, be = coeffs(n, dt, mode)
+    inside = not dealias or max(abs(m) for m in mode) <= n // 3
+    th = np.arccos((al + (be * amp * amp if inside else 0.0)) / 2)
+    with kg.Solver(n, dt, precision=precision, complex_field=True, dealias=dealias) as s:
+        s.set_state(device_wave(torch, n, mode, 0.0, amp), device_wave(torch, n, mode, th, amp),
+                    kg.KG_INIT_TWO_LEVEL)
+        s.step(steps)
+        out = torch.empty((n, n, n), dtype=torch.complex128, device="cuda")
+        s.u(out)
+        err = (out - device_wave(torch, n, mode, -steps * th, amp)).abs().max().item()
+        _, _, maxu = s.records(0, steps)
+    assert err <= tol * amp
+    assert np.allclose(maxu, amp, rtol=10 * tol)
+
+
+def test_real_data_as_complex_field_at_512(kg):
+    """The 512^3 benchmark Gaussian stepped as a complex field matches the
+    real path (full-spectrum vs half-spectrum kernels) after 20 steps."""
+    import torch
+    n, dt, steps = 512, 0.005, 20
+    x = torch.tensor(ki.axis(n), device="cuda", dtype=torch.float64)
+    r2 = (x * x)[:, None, None] + (x * x)[None, :, None] + (x * x)[None, None, :]
+    u0 = (1.5 * torch.exp(-r2)).contiguous()
+    outs = []
+    for cf in (False, True):
+        with kg.Solver(n, dt, complex_field=cf) as s:
+            s.set_state(u0.to(torch.complex128).contiguous() if cf else u0)
+            s.step(steps)
+            out = torch.empty((n, n, n), dtype=torch.complex128 if cf else torch.float64,
+                              device="cuda")
+            s.u(out)
+            outs.append((out, s.energy()[0]))
+    (ur, Er), (uc, Ec) = outs
+    scale = ur.abs().max().item()
+    assert (uc.real - ur).abs().max().item() <= 1e-12 * scale
+    assert uc.imag.abs().max().item() <= 1e-12 * scale
+    assert abs(Ec - Er) <= 1e-12 * abs(Er)
