@@ -244,14 +244,45 @@ __device__ __forceinline__ void twiddles(cx<T> (&w)[R], const cx<T> *__restrict_
     }
 }
 
+// Twiddle base values (w, w^2, w^4) of every twiddled stage of a line,
+// loaded into registers ahead of the transform: the stages then wait on no
+// memory.  Only for lines whose twiddled stages are all radix 8 with one
+// butterfly per thread, i.e. 2^a lines of at least 16 points (their only
+// non-radix-8 stage is the first, which needs no twiddles).
+template <typename T, int NL>
+struct TwPre {
+    static constexpr bool OK = !Radix<NL>::THREE && Radix<NL>::E == 8 && NL >= 16;
+    cx<T> w[Radix<NL>::NST][3];
+};
+
+template <typename T, int NL, int S = 1>
+__device__ __forceinline__ void twiddle_preload(TwPre<T, NL> &p, const cx<T> *__restrict__ tw,
+                                                int t, int twm)
+{
+    using P = Radix<NL>;
+    static_assert(TwPre<T, NL>::OK, "twiddle preloading needs radix-8 twiddled stages");
+    if constexpr (S < P::NST) {
+        constexpr int R = P::radix(S), L = P::lbefore(S);
+        static_assert(R == 8, "twiddled stages must be radix 8");
+        const int idx = (t % L) * (NL / (L * R)) * twm;
+        p.w[S][0] = tw[idx];
+        p.w[S][1] = tw[2 * idx];
+        p.w[S][2] = tw[4 * idx];
+        twiddle_preload<T, NL, S + 1>(p, tw, t, twm);
+    }
+}
+
 // Stockham stages S..NST-1 of a line.  v holds the owned positions on entry
 // to stage 0 and on exit from the last stage.  lds points at slot 0 of this
 // line in an LDS buffer where consecutive slots are `ls` elements apart (the
 // line needs lslots<NL>() slots).  tw is the table exp(-2 pi i j / NTAB) with
 // NTAB = NL * twm.  Callers must make sure nobody still reads the LDS line.
+// With a TwPre (pre non-null) the twiddles come from its registers instead
+// of the table.
 template <typename T, int NL, int DIR, int SY = SYNC_BLOCK, int SH = 3, int S = 0>
 __device__ __forceinline__ void fft_line(cx<T> (&v)[Radix<NL>::E], cx<T> *lds, int ls, int t,
-                                         const cx<T> *__restrict__ tw, int twm)
+                                         const cx<T> *__restrict__ tw, int twm,
+                                         const TwPre<T, NL> *pre = nullptr)
 {
 #pragma clang fp contract(off)
     using P = Radix<NL>;
@@ -273,7 +304,21 @@ __device__ __forceinline__ void fft_line(cx<T> (&v)[Radix<NL>::E], cx<T> *lds, i
         for (int r = 0; r < R; ++r) x[r] = v[b + r * (E / R)];
         if constexpr (L > 1) {
             cx<T> w[R];
-            twiddles<R>(w, tw, k * (NL / (L * R)) * twm);
+            if constexpr (R == 8 && TwPre<T, NL>::OK) {
+                if (pre) {
+                    w[1] = pre->w[S][0];
+                    w[2] = pre->w[S][1];
+                    w[3] = cmul(w[1], w[2]);
+                    w[4] = pre->w[S][2];
+                    w[5] = cmul(w[1], w[4]);
+                    w[6] = cmul(w[2], w[4]);
+                    w[7] = cmul(w[3], w[4]);
+                } else {
+                    twiddles<R>(w, tw, k * (NL / (L * R)) * twm);
+                }
+            } else {
+                twiddles<R>(w, tw, k * (NL / (L * R)) * twm);
+            }
 #pragma unroll
             for (int r = 1; r < R; ++r) x[r] = (DIR < 0) ? cmul(x[r], w[r]) : cmulc(x[r], w[r]);
         }
@@ -287,7 +332,7 @@ __device__ __forceinline__ void fft_line(cx<T> (&v)[Radix<NL>::E], cx<T> *lds, i
             for (int s = 0; s < R; ++s) lds[lpos<SH>(base + s * L) * ls] = x[s];
         }
     }
-    if constexpr (!last) fft_line<T, NL, DIR, SY, SH, S + 1>(v, lds, ls, t, tw, twm);
+    if constexpr (!last) fft_line<T, NL, DIR, SY, SH, S + 1>(v, lds, ls, t, tw, twm, pre);
 }
 
 }  // namespace kg
