@@ -49,11 +49,16 @@ class Solver:
         self.close()
 
     def set_state(self, u0, aux=None, mode=_kg.KG_INIT_VELOCITY):
-        want = (np.complex128, torch.complex128) if self.complex_field else (np.float64,
-                                                                             torch.float64)
         for x in (u0, aux):
-            if x is not None and x.dtype not in want:
-                raise TypeError(f"initial data of dtype {x.dtype}; this run takes {want[0]}")
+            if x is None:
+                continue
+            if isinstance(x, np.ndarray):
+                ok = x.dtype == (np.complex128 if self.complex_field else np.float64)
+            else:
+                ok = x.dtype == (torch.complex128 if self.complex_field else torch.float64)
+            if not ok:
+                raise TypeError(f"initial data of dtype {x.dtype}; this run takes "
+                                f"{'complex128' if self.complex_field else 'float64'}")
         _kg.kg_set_state(self.plan, u0, aux, mode)
 
     def step(self, nsteps, sync=True):
