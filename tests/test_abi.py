@@ -69,3 +69,47 @@ def test_plan_setup_runs_on_the_host():
             with pytest.raises(kg.KGError) as e:
                 kg.kg_plan(kg.make_params(n, 0.01, precision=prec))
             assert e.value.status in (kg.KG_E_NOMEM, kg.KG_E_HIP)
+
+
+def test_ctypes_structs_match_the_header(tmp_path):
+    """The binding's ctypes mirrors of the header's structs have the C field
+    offsets and sizes (a C program built against include/kg.h prints them)."""
+    import json
+    import subprocess
+    from paper_1501_04552_amd import kg
+    structs = {"kg_params": kg.kg_params, "kg_run_desc": kg.kg_run_desc,
+               "kg_run_result": kg.kg_run_result, "kg_batch_opts": kg.kg_batch_opts}
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "kg.h"', "int main(void) {",
+             '  printf("{");']
+    first = True
+    for name, cls in structs.items():
+        for field, _ in cls._fields_:
+            sep = "" if first else ","
+            first = False
+            lines.append(f'  printf("{sep}\\"{name}.{field}\\": %zu", offsetof({name}, {field}));')
+        lines.append(f'  printf(",\\"{name}\\": %zu", sizeof({name}));')
+    lines += ['  printf("}\\n");', "  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    c = json.loads(subprocess.run([str(exe)], check=True, capture_output=True,
+                                  text=True).stdout)
+    for name, cls in structs.items():
+        assert c[name] == ctypes.sizeof(cls), name
+        for field, _ in cls._fields_:
+            assert c[f"{name}.{field}"] == getattr(cls, field).offset, (name, field)
+
+
+def test_complex_field_workspace():
+    """A complex field holds the full spectrum, n columns against the real
+    field's n/2 + 1 padded to whole tiles (136 in FP64, 144 in FP32 at 256^3):
+    1.7 to 2 times the real workspace."""
+    from paper_1501_04552_amd import kg
+    for prec in (kg.KG_FP64, kg.KG_FP32):
+        br = kg.kg_workspace_bytes(kg.make_params(256, 0.01, precision=prec))
+        bc = kg.kg_workspace_bytes(kg.make_params(256, 0.01, precision=prec, complex_field=True))
+        assert 1.7 * br < bc < 2.05 * br
+        bd = kg.kg_workspace_bytes(kg.make_params(256, 0.01, precision=prec, dealias=True))
+        assert bd == br
