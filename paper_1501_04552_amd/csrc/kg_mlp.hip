@@ -3,7 +3,7 @@
 // logit and a standardised log blow-up time, with hand-written forward,
 // backward and Adam kernels.  Parametric blow-up studies are the paper's
 // motivation (Sec. 1); the network is trained on runs of the solver and the
-// solver remains the judge (low-confidence answers are rerun).
+// solver remains the arbiter (low-confidence answers are rerun).
 //
 // Loss over a batch of B samples with labels y_b (1 = blow-up) and targets
 // t_b (used where y_b = 1):

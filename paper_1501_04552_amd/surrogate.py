@@ -6,7 +6,7 @@ Gaussian initial data u0 = A exp(-(x^2/sx^2 + y^2/sy^2 + z^2/sz^2)) (blow-up
 or not, and the blow-up time), a small MLP trained by the library's own HIP
 kernels learns the map (A, sx, sy, sz) -> (blow-up logit, log blow-up time),
 and queries the network is not confident about (|logit| < 2) are answered by
-rerunning the solver, which remains the judge of every error reported.
+rerunning the solver, which remains the arbiter of every error reported.
 """
 import time
 
