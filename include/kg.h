@@ -280,20 +280,23 @@ kg_status kg_mlp_train_step(kg_mlp_t *m, const float *d_x, const float *d_y, int
 
 /*
  * Full forward 3D r2c transform of a real field through the solver's own
- * kernels (x r2c, y, z): half spectrum as in kg_get_spectrum.  The solver
- * state is clobbered (call kg_set_state afterwards).
+ * kernels (x r2c, y, z): half spectrum as in kg_get_spectrum (for a complex
+ * field plan: c2c of an interleaved complex field, full spectrum).  The
+ * solver state is clobbered (call kg_set_state afterwards).
  */
 kg_status kg_debug_forward(kg_plan_t *plan, const double *u, double *spec, int on_device);
 
 /*
  * Full inverse 3D c2r transform (z, y, x c2r), unnormalised: returns
  * Re sum_k X_k exp(+2 pi i k.j / n) over the Hermitian completion of the
- * given half spectrum.  Clobbers the solver state.
+ * given half spectrum (for a complex field plan: the c2c inverse of a full
+ * spectrum, an interleaved complex field).  Clobbers the solver state.
  */
 kg_status kg_debug_inverse(kg_plan_t *plan, const double *spec, double *u, int on_device);
 
 /*
- * One pass on a half spectrum in [z][y][kx] order (n/2+1 values per row):
+ * One pass on a half spectrum in [z][y][kx] order (n/2+1 values per row; n
+ * for a complex field plan):
  * pass 1 = forward c2c along y, 2 = inverse along y, 3 = forward along z,
  * 4 = inverse along z.  In place on `spec`.  Clobbers the solver state.
  */
