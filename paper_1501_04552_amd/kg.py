@@ -14,7 +14,7 @@ import torch  # noqa: F401  (load PyTorch's HIP runtime before the library)
 from .build import LIB
 
 if not os.path.exists(LIB):
-    raise ImportError(f"{LIB} is missing: build it with `python -m paper_1501_04552_amd.build` "
+    raise ImportError(f"{LIB} is missing: build it with `python paper_1501_04552_amd/build.py` "
                       "or __graft_entry__.build()")
 
 _lib = ctypes.CDLL(LIB)
