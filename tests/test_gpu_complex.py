@@ -282,3 +282,24 @@ def test_real_data_as_complex_field_at_512(kg):
     assert (uc.real - ur).abs().max().item() <= 1e-12 * scale
     assert uc.imag.abs().max().item() <= 1e-12 * scale
     assert abs(Ec - Er) <= 1e-12 * abs(Er)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_kernel_bytes_and_times_of_complex_plans(kg, precision):
+    """The algorithmic bytes the bench divides by: one sweep is every stored
+    spectral value once (n^3 for a complex field, n^2 (n/2+1) for a real one);
+    the z pass moves 5 sweeps in FP64 and 6 in FP32, the others 2."""
+    n = 64
+    esz = 16 if precision == 0 else 8
+    for cf, values in ((True, n ** 3), (False, n * n * (n // 2 + 1))):
+        with kg.Solver(n, 0.01, precision=precision, complex_field=cf) as s:
+            sweep = values * esz
+            assert kg.kg_kernel_bytes(s.plan, 2) == (5 if precision == 0 else 6) * sweep
+            for k in (0, 1, 3):
+                assert kg.kg_kernel_bytes(s.plan, k) == 2 * sweep
+            z, y, x = ki.mesh(n, L)
+            u0 = ki.gaussian(n, 0.5) * (np.exp(0.5j * x) if cf else 1.0)
+            s.set_state(u0)
+            kg.kg_step(s.plan, 3, kg.KG_STEP_TIMED)
+            ms, steps = kg.kg_kernel_times(s.plan)
+            assert steps == 3 and all(t > 0 for t in ms)
