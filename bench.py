@@ -7,12 +7,18 @@ the inverse y pass, the x pass with the cubic term and the forward y pass,
 then the z pass with the update and energy, then the finalize.  The initial
 field is resident in HBM before timing starts.
 
-Prints one JSON line.  Also reports the dominant kernel's roofline figures
-(its algorithmic bytes over its average launch time, measured with HIP
-events inside the timed steps) and the CPU oracle timed on a bounded sample
-(three 512^3 steps) on this host.  Secondary legs: the FP32 path, a complex
-field (u0 times the phase exp(i x / 2), cubic term |u|^2 u) in both
-precisions, and the batched parametric sweep.
+Prints one JSON line.  `value` = steps / wall time of exactly --steps steps
+bracketed by device synchronisations, after --warmup untimed steps; the step
+graphs are captured when the state is set, so no capture or set-up falls in
+the timed region.  Also reported: the median over 5 repetitions of a 50-step
+run timed by HIP events on the solver's stream; the dominant kernel's
+roofline figures (its algorithmic bytes over its average launch time,
+measured with HIP events); and the CPU oracle, built for this host, timed on
+a bounded sample on this host's cores (all threads, and one thread).
+Secondary legs: the FP32 path, the precision study against the oracle's
+reference fields, a complex field (u0 times the phase exp(i x / 2), cubic
+term |u|^2 u) in both precisions, the batched parametric sweep and the
+blow-up surrogate.
 """
 import argparse
 import json
@@ -39,6 +45,11 @@ def parse():
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--sweep-runs", type=int, default=512)
     ap.add_argument("--sweep-seq-sample", type=int, default=16)
+    ap.add_argument("--surrogate", choices=("off", "small", "full"), default="small",
+                    help="surrogate leg: off, small (2048 training / 512 held-out runs), or "
+                         "full (8192 / 1024 runs)")
+    ap.add_argument("--event-reps", type=int, default=5)
+    ap.add_argument("--event-steps", type=int, default=50)
     ap.add_argument("--complex", choices=("on", "off", "only"), default="on",
                     help="complex-field legs: with the real ones (on), none (off), or alone "
                          "(only: one JSON line for the complex FP64 leg, for profiling)")
@@ -107,16 +118,121 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def cpu_baseline(u0, dt, steps=3):
-    """The oracle on this host: a few steps of the same workload (set-up
-    excluded; about 12 s at 512^3 on 16 threads)."""
+def cpu_model():
+    """The host CPU's model name (lscpu, else /proc/cpuinfo)."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    return None
+
+
+def native_oracle():
+    """Path of the oracle compiled for this host (-O3 -march=native -fopenmp)."""
+    import tempfile
+    from oracle.build import build_oracle
+    d = tempfile.mkdtemp(prefix="kg_oracle_native_")
+    return build_oracle(out=os.path.join(d, "libkg_oracle_native.so"),
+                        opt=("-O3", "-march=native"))
+
+
+ONE_THREAD_CODE = """
+import json, sys
+sys.path.insert(0, {root!r})
+import oracle, kg_inputs as ki
+o = oracle.Oracle({lib!r})
+r = o.run(ki.gaussian({n}, {A}), {dt}, {steps})
+print(json.dumps({{"seconds": r["loop_seconds"], "threads": o.num_threads()}}))
+"""
+
+
+def start_one_thread_baseline(lib, n, A, dt, steps=1):
+    """The oracle on one host thread, in a child process (its set-up alone
+    takes about a minute at 512^3, so it runs while the GPU legs do)."""
+    import subprocess
+    code = ONE_THREAD_CODE.format(root=ROOT, lib=lib, n=n, A=A, dt=dt, steps=steps)
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    return subprocess.Popen([sys.executable, "-c", code], env=env, stdout=subprocess.PIPE,
+                            stderr=subprocess.PIPE, text=True)
+
+
+def cpu_baseline(lib, u0, dt, one_thread, steps=5):
+    """The oracle on this host's cores: `steps` steps of the same workload on
+    all threads (set-up excluded), plus the one-thread child's result."""
     import oracle
-    r = oracle.run(u0, dt, steps)
+    o = oracle.Oracle(lib)
+    r = o.run(u0, dt, steps)
     secs = r["loop_seconds"]
-    return {"value": steps / secs if secs > 0 else None, "unit": "steps/s",
-            "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{steps} time steps of the {u0.shape[0]}^3 FP64 workload (set-up "
-                      f"excluded), {secs:.2f} s"}
+    out = {"value": steps / secs if secs > 0 else None, "unit": "steps/s",
+           "cores": o.num_threads(), "kind": "oracle", "cpu_model": cpu_model(),
+           "build": "gcc -O3 -march=native -fopenmp on this host",
+           "sample": f"{steps} time steps of the {u0.shape[0]}^3 FP64 workload (set-up "
+                     f"excluded), {secs:.2f} s on {o.num_threads()} threads"}
+    if one_thread is not None:
+        so, se = one_thread.communicate(timeout=900)
+        if one_thread.returncode == 0:
+            d = json.loads(so.strip().splitlines()[-1])
+            out["one_thread"] = {"value": 1.0 / d["seconds"], "unit": "steps/s",
+                                 "threads": d["threads"],
+                                 "sample": f"1 time step of the same workload, "
+                                           f"{d['seconds']:.1f} s"}
+        else:
+            out["one_thread"] = {"error": se[-500:]}
+    return out
+
+
+def golden_compare(kg, ki, np, torch, n, A, steps=200):
+    """The precision workload (A = 1.5, sigma = 1, dt = 0.005, 200 steps) in
+    both precisions, each against the oracle's reference field and energies
+    (tests/golden/field_<n>_A1.5.npz, written from oracle/ only): relative
+    L2 over the stored samples (strided 32^3 and central 16^3) and the energy
+    drift of the run."""
+    path = os.path.join(ROOT, "tests", "golden", f"field_{n}_A{A:g}.npz")
+    if not os.path.exists(path):
+        return None
+    g = np.load(path)
+    out = {"workload": f"{n}^3 A={A} sigma=1 dt={float(g['dt'])} {steps} steps; u compared on "
+                       "a strided 32^3 subsample and the central 16^3 block",
+           "energy_drift_oracle": float(abs(g["energy"][steps] - g["energy"][0]) /
+                                        abs(g["energy"][0]))}
+    for name, prec in (("fp64", kg.KG_FP64), ("fp32", kg.KG_FP32)):
+        with kg.Solver(n, float(g["dt"]), precision=prec) as s:
+            s.set_state(torch.from_numpy(ki.gaussian(n, A)).cuda())
+            s.step(steps)
+            u = torch.empty((n, n, n), dtype=torch.float64, device="cuda")
+            s.u(u)
+            st, c = n // 32, n // 2
+            got = np.concatenate([u[::st, ::st, ::st].cpu().numpy().ravel(),
+                                  u[c - 8:c + 8, c - 8:c + 8, c - 8:c + 8].cpu().numpy().ravel()])
+            del u
+            E = s.energies(0, steps + 1)
+        ref = np.concatenate([g[f"u{steps}_sub"].ravel(), g[f"u{steps}_center"].ravel()])
+        out[name] = {"rel_l2_vs_oracle": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
+                     "energy_max_rel_diff_vs_oracle":
+                         float(np.max(np.abs(E - g["energy"][:steps + 1]) /
+                                      np.abs(g["energy"][:steps + 1]))),
+                     "energy_drift": float(abs(E[-1] - E[0]) / abs(E[0]))}
+    return out
+
+
+def surrogate_leg(mode):
+    """The blow-up surrogate on the sweep distribution at 64^3: solver labels,
+    training by the library's kernels, held-out accuracy with solver fallback,
+    and the cost of building it (labelling + training) against the time it
+    saves per query (break-even query count)."""
+    from paper_1501_04552_amd import surrogate as sg
+    ntr, nte = (8192, 1024) if mode == "full" else (2048, 512)
+    return sg.main(["--train", str(ntr), "--test", str(nte), "--quiet"])
 
 
 def main():
@@ -137,8 +253,9 @@ def main():
     u0_dev = torch.from_numpy(u0).cuda()
 
     def timed_run(precision, complex_field=False):
-        """Warm up, time args.steps steps (graph replays), then an event-timed
-        run of the same length for per-kernel durations."""
+        """Warm up, time args.steps steps (graph replays) between device
+        synchronisations, repeat a 50-step run timed by HIP events, then an
+        event-per-kernel run of the same length for per-kernel durations."""
         solver = kg.Solver(n, dt, blowup_threshold=1e3, precision=precision,
                            complex_field=complex_field)
         if complex_field:
@@ -146,7 +263,14 @@ def main():
             solver.set_state((u0_dev.to(torch.complex128) * torch.exp(0.5j * x)).contiguous())
         else:
             solver.set_state(u0_dev)
-        E0, _ = solver.energy()
+        # set-up, outside the timed region: set_state captured and uploaded the
+        # step graphs; launch each once (8-step and single-step, both level
+        # parities), then start the run again from the initial data
+        solver.step(2 * 8 + 2, sync=True)
+        if complex_field:
+            solver.set_state((u0_dev.to(torch.complex128) * torch.exp(0.5j * x)).contiguous())
+        else:
+            solver.set_state(u0_dev)
         solver.step(args.warmup, sync=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -156,16 +280,27 @@ def main():
         done, blown, _ = solver.stats()
         if blown:
             raise RuntimeError("the benchmark run blew up")
-        elin, q4, _ = solver.records(0, done)
-        series = [(m, float(elin[m] - (q4[m] + q4[m + 1]) / 8.0))
-                  for m in range(0, done - 1, args.energy_every)]
-        E_end, _ = solver.energy()
+        # energy E^{m-1/2} every args.energy_every levels, through the library
+        levels = list(range(0, done + 1, args.energy_every))
+        if levels[-1] != done:
+            levels.append(done)
+        series = [(m, float(solver.energies(m, 1)[0])) for m in levels]
+        drift = abs(series[-1][1] - series[0][1]) / abs(series[0][1])
+        # HIP events on the solver's stream around repeated graph runs
+        ev_ms = []
+        for _ in range(args.event_reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(solver.stream)
+            kg.kg_step(solver.plan, args.event_steps, 0)
+            e1.record(solver.stream)
+            e1.synchronize()
+            ev_ms.append(e0.elapsed_time(e1) / args.event_steps)
         kg.kg_step(solver.plan, args.steps, kg.KG_STEP_TIMED)
         ms, _ = kg.kg_kernel_times(solver.plan)
         kbytes = [kg.kg_kernel_bytes(solver.plan, i) for i in range(4)]
         solver.close()
-        return dict(elapsed=elapsed, series=series, drift=abs(E_end - E0) / abs(E0), ms=ms,
-                    kbytes=kbytes)
+        return dict(elapsed=elapsed, series=series, drift=drift, ms=ms, kbytes=kbytes,
+                    event_ms=float(np.median(ev_ms)), event_ms_all=ev_ms)
 
     def complex_legs():
         out = {}
@@ -202,9 +337,13 @@ def main():
     # the FP64 solver measured about 2% slower; FP64 does not depend on it)
     r32 = timed_run(kg.KG_FP32)
     r64 = timed_run(kg.KG_FP64)
+    one_thread, oracle_lib = None, None
+    if not args.no_cpu_baseline and n <= 512:
+        oracle_lib = native_oracle()
+        one_thread = start_one_thread_baseline(oracle_lib, n, args.amplitude, dt)
     cplx = complex_legs() if args.complex == "on" else None
     for m, e in r64["series"]:
-        print(f"step {m:5d}  E^(m+1/2) = {e:.15e}", file=sys.stderr)
+        print(f"step {m:5d}  E^(m-1/2) = {e:.15e}", file=sys.stderr)
     elapsed, drift, ms = r64["elapsed"], r64["drift"], r64["ms"]
     zi = kg.KERNELS.index("z_update")
     zbytes = r64["kbytes"][zi]
@@ -212,19 +351,10 @@ def main():
     kernels = {name: {"ms": ms[i], "GB/s": (r64["kbytes"][i] / (ms[i] * 1e-3) / 1e9
                                             if i < 4 and ms[i] > 0 else None)}
                for i, name in enumerate(kg.KERNELS)}
+    z32 = r32["kbytes"][zi] / (r32["ms"][zi] * 1e-3) / 1e9
 
-    # precision study: A = 1.5, sigma = 1, dt = 0.005, 200 steps, FP32 vs FP64
-    ua = ki.gaussian(n, 1.5)
-    res = {}
-    for prec in (kg.KG_FP64, kg.KG_FP32):
-        with kg.Solver(n, dt, precision=prec) as s:
-            s.set_state(ua)
-            Ea, _ = s.energy()
-            s.step(200)
-            res[prec] = (s.u(), abs(s.energy()[0] - Ea) / abs(Ea))
-    rel32 = float(np.linalg.norm(res[1][0] - res[0][0]) / np.linalg.norm(res[0][0]))
-    drift_a = {"fp64": res[0][1], "fp32": res[1][1]}
-    del ua, res
+    # precision study against the oracle's reference fields (A = 1.5, 200 steps)
+    precision_study = {str(m): golden_compare(kg, ki, np, torch, m, 1.5) for m in (256, n)}
     # achievable-bandwidth ceiling: the library's plain copy kernel, 1 GiB
     nb = 1 << 30
     src = torch.empty(nb, dtype=torch.uint8, device="cuda")
@@ -240,14 +370,14 @@ def main():
     t32 = r32["elapsed"] / args.steps
     fp32 = {"steps_per_s": 1.0 / t32, "ms_per_step": 1e3 * t32,
             "speedup_vs_fp64": (1.0 / t32) / steps_per_s,
+            "event_median_ms_per_step": r32["event_ms"],
+            "speedup_vs_fp64_event_median": r64["event_ms"] / r32["event_ms"],
             "step_model_GBs": 12 * sweep_b / 2 / t32 / 1e9,
             "step_hbm_frac": 12 * sweep_b / 2 / t32 / 1e9 / HBM_PEAK_GBS,
             "kernels_ms": dict(zip(kg.KERNELS, r32["ms"])),
-            "energy_drift": r32["drift"],
-            "precision_study": {"workload": f"{n}^3 A=1.5 sigma=1 dt={dt} 200 steps",
-                                "rel_l2_fp32_vs_fp64": rel32,
-                                "energy_drift_fp64": drift_a["fp64"],
-                                "energy_drift_fp32": drift_a["fp32"]}}
+            "kernels_ms_sum": float(sum(r32["ms"])),
+            "z_update_GBs": z32, "z_update_hbm_frac": z32 / HBM_PEAK_GBS,
+            "energy_drift": r32["drift"]}
     line = {
         "metric": "512^3 time steps/s (FP64)" if n == 512 else f"{n}^3 time steps/s (FP64)",
         "value": steps_per_s,
@@ -268,6 +398,10 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": z_gbs / HBM_PEAK_GBS,
                      "traffic": traffic_from_profiles(n),
                      "algorithmic_bytes_per_launch": zbytes, "avg_launch_ms": ms[zi]},
+        "event_median_ms_per_step": r64["event_ms"],
+        "event_ms_per_step_reps": r64["event_ms_all"],
+        "event_timing": f"median of {args.event_reps} runs of {args.event_steps} steps, HIP "
+                        "events on the solver's stream",
         "step_model_GBs": step_bytes / (elapsed / args.steps) / 1e9,
         "step_hbm_frac": step_bytes / (elapsed / args.steps) / 1e9 / HBM_PEAK_GBS,
         "step_model_note": "11 algorithmic sweeps of the half spectrum per step over the step "
@@ -275,16 +409,20 @@ def main():
                            "256 MB memory-side cache serves in part, so this is an effective "
                            "rate, not HBM traffic",
         "kernels": kernels,
+        "kernels_ms_sum": float(sum(ms)),
         "copy_GBs": copy_gbs,
         "energy_drift": drift,
         "fp32": fp32,
+        "precision_study": precision_study,
     }
     if cplx:
         line["complex_field"] = cplx
     if not args.no_sweep:
         line["sweep"] = sweep(args, kg, ki, torch)
-    if not args.no_cpu_baseline and n <= 512:
-        line["cpu_baseline"] = cpu_baseline(u0, dt)
+    if args.surrogate != "off":
+        line["surrogate"] = surrogate_leg(args.surrogate)
+    if oracle_lib:
+        line["cpu_baseline"] = cpu_baseline(oracle_lib, u0, dt, one_thread)
     print(json.dumps(line), flush=True)
 
 

@@ -125,13 +125,16 @@ kg_status kg_set_state(kg_plan_t *plan, const double *u0, const double *aux, int
 
 /*
  * Enqueue nsteps steps of eq. (2).  Asynchronous unless flags has
- * KG_STEP_SYNC.  After each step the max|u^n| of the level just used is
- * checked; on a blow-up the remaining kernels return at once and the
- * counter stops at the blown level n.  With KG_STEP_SYNC the call
- * synchronises, stores the step counter in *steps_done (may be NULL) and
- * returns KG_BLOWUP if the run has blown up.  With KG_STEP_TIMED every kernel
- * launch of the call is bracketed by HIP events on the plan's stream and the
- * call synchronises; kg_kernel_times then reports the per-kernel averages.
+ * KG_STEP_SYNC.  Steps are replayed from hipGraphs (8 steps, then single
+ * steps) that kg_set_state / kg_load_state capture, so a call launches no
+ * kernel from the host and never captures.  After each step the max|u^n|
+ * of the level just used is checked; on a blow-up the remaining kernels
+ * return at once and the counter stops at the blown level n.  With
+ * KG_STEP_SYNC the call synchronises, stores the step counter in
+ * *steps_done (may be NULL) and returns KG_BLOWUP if the run has blown up.
+ * With KG_STEP_TIMED the kernels are launched one by one instead, every
+ * launch bracketed by HIP events on the plan's stream, and the call
+ * synchronises; kg_kernel_times then reports the per-kernel averages.
  */
 kg_status kg_step(kg_plan_t *plan, int nsteps, unsigned flags, int *steps_done);
 
@@ -148,9 +151,22 @@ kg_status kg_kernel_times(const kg_plan_t *plan, double ms[5], int *nsteps);
  *   E^{n-1/2} = (h^3/(2M)) sum_k [|v^n - v^{n-1}|^2/dt^2 + (1+|k|^2)|v^n + v^{n-1}|^2/4]
  *               - chi (Q4^{n-1} + Q4^n) / 8,   Q4^m = h^3 sum_j |u^m_j|^4,
  * (M = n^3, h = L/n, chi = 0 for the linear equation), at time t = (n - 1/2) dt.
- * Synchronises the stream.  E or t may be NULL.
+ * The discrete form is this library's reading of the continuous energy; its
+ * linear part is exactly conserved by eq. (2).  Q4^n is reduced on demand
+ * (one read-only pass over the field); the stepping path never pays for it.
+ * Synchronises the stream.  E or t may be NULL.  KG_BLOWUP after a blow-up.
  */
 kg_status kg_energy(kg_plan_t *plan, double *E, double *t);
+
+/*
+ * Energy series: E[i] = E^{m-1/2} (the kg_energy formula for the pair
+ * (v^{m-1}, v^m)) for levels m = first .. first+count-1, where m ranges over
+ * 0 .. steps done (m = 0 is the initial pair (v^{-1}, v^0)).  After a
+ * blow-up at level b every m <= b is available.  E is a host array of count
+ * doubles.  Levels older than the 65535 retained records, or beyond the
+ * newest, give KG_E_INVALID.  Synchronises.
+ */
+kg_status kg_energies(kg_plan_t *plan, int first, int count, double *E);
 
 /*
  * Per-step records for levels first..first+count-1 (each level m < steps
@@ -161,21 +177,46 @@ kg_status kg_energy(kg_plan_t *plan, double *E, double *t);
 kg_status kg_records(kg_plan_t *plan, int first, int count, double *elin, double *q4,
                      double *maxu);
 
-/* Steps done, blow-up flag and blown level (-1 if none).  Synchronises. */
-kg_status kg_stats(kg_plan_t *plan, int *steps_done, int *blown_up, int *blowup_step);
+/*
+ * Steps done, blow-up flag and blown level (-1 if none), and max_j |u^n_j|
+ * of the newest level n (the blown level after a blow-up; NaN if that level
+ * holds a non-finite value).  Any output may be NULL; max_abs_u costs one
+ * read-only pass over the field unless the run has blown up.  Synchronises.
+ */
+kg_status kg_stats(kg_plan_t *plan, int *steps_done, int *blown_up, int *blowup_step,
+                   double *max_abs_u);
 
 /* u^n (n = steps done) in physical space, n^3 doubles (2*n^3 interleaved
- * re, im for a complex field).  Off the hot path. */
+ * re, im for a complex field).  Off the hot path.  Same as
+ * kg_get_state(plan, NULL, u_out, on_device). */
 kg_status kg_get_u(kg_plan_t *plan, double *u_out, int on_device);
+
+/*
+ * The two time levels eq. (2) advances, in physical space: u_prev = u^{n-1},
+ * u_cur = u^n (n = steps done), each a field as in kg_get_u; either may be
+ * NULL (not both).  kg_set_state(plan, u_cur, u_prev, KG_INIT_TWO_LEVEL, .)
+ * restarts the run from them (equal to the uninterrupted run up to the
+ * rounding of one transform pair, ~1e-15 relative in FP64).  After a
+ * blow-up u_prev is unavailable (the blown step has overwritten it):
+ * KG_E_INVALID.  FP32 plans store (v^n, v^n - v^{n-1}) in float: u^{n-1} is
+ * formed from the increment, and after a blow-up at level b the stored pair
+ * is (v^{b+1}, v^{b+1} - v^b), so u^b carries the float rounding of the
+ * (much larger) v^{b+1}.
+ */
+kg_status kg_get_state(kg_plan_t *plan, double *u_prev, double *u_cur, int on_device);
 
 /*
  * Spectrum of a stored level: which = 0 gives v^n, which = 1 gives v^{n-1}
  * (n = steps done), as the half spectrum described above (n*n*(n/2+1)
  * complex values, 2 doubles each; the full n*n*n spectrum for a complex field).
+ * After a blow-up, which = 1 gives KG_E_INVALID: the blown step has already
+ * overwritten v^{n-1}.
  */
 kg_status kg_get_spectrum(kg_plan_t *plan, int which, double *out, int on_device);
 
-/* Raw state (both levels, step counter): size, save and bitwise resume. */
+/* Raw state (both levels, step counter): size, save and bitwise resume.
+ * The saved buffer is opaque and only loads into a plan of the same
+ * parameters.  A state saved after a blow-up reloads as blown. */
 size_t kg_state_bytes(const kg_plan_t *plan);
 kg_status kg_save_state(kg_plan_t *plan, void *host_buf, size_t bytes);
 kg_status kg_load_state(kg_plan_t *plan, const void *host_buf, size_t bytes);

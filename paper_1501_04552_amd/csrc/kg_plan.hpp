@@ -42,9 +42,9 @@ struct kg_plan_s {
     std::vector<hipEvent_t> tev;  // events of KG_STEP_TIMED calls
     hipStream_t cap = nullptr;    // private stream used only to capture graphs
     hipStream_t cap2 = nullptr;   // second capture stream: odd slabs of the chain
-    hipStream_t side = nullptr;   // second stream of eagerly launched steps
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-    hipGraphExec_t gexec[2] = {nullptr, nullptr};  // GRAPH_STEPS steps from parity 0 / 1
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};   // GRAPH_STEPS steps from parity 0 / 1
+    hipGraphExec_t gexec1[2] = {nullptr, nullptr};  // one step from parity 0 / 1
     double kt_ms[5] = {0, 0, 0, 0, 0};
     int kt_steps = 0;
     std::string err;

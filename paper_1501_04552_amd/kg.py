@@ -69,8 +69,10 @@ _SIGS = {
     "kg_step": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_uint, _ip]),
     "kg_energy": (ctypes.c_int, [_vp, _dp, _dp]),
     "kg_records": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]),
-    "kg_stats": (ctypes.c_int, [_vp, _ip, _ip, _ip]),
+    "kg_energies": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp]),
+    "kg_stats": (ctypes.c_int, [_vp, _ip, _ip, _ip, _dp]),
     "kg_get_u": (ctypes.c_int, [_vp, _vp, ctypes.c_int]),
+    "kg_get_state": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int]),
     "kg_get_spectrum": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.c_int]),
     "kg_state_bytes": (ctypes.c_size_t, [_vp]),
     "kg_save_state": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t]),
@@ -187,9 +189,21 @@ def kg_records(plan, first, count):
     return elin, q4, maxu
 
 
-def kg_stats(plan):
-    s, b, bs = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
-    _check(_lib.kg_stats(plan, ctypes.byref(s), ctypes.byref(b), ctypes.byref(bs)), plan)
+def kg_energies(plan, first, count):
+    """E^{m-1/2} for levels m = first .. first+count-1 (host array)."""
+    E = np.empty(count)
+    _check(_lib.kg_energies(plan, first, count, E.ctypes.data), plan)
+    return E
+
+
+def kg_stats(plan, max_abs_u=False):
+    """(steps done, blown up, blown level or -1), plus max|u^n| of the newest
+    level when max_abs_u is true."""
+    s, b, bs, mx = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+    _check(_lib.kg_stats(plan, ctypes.byref(s), ctypes.byref(b), ctypes.byref(bs),
+                         ctypes.byref(mx) if max_abs_u else None), plan)
+    if max_abs_u:
+        return s.value, bool(b.value), bs.value, mx.value
     return s.value, bool(b.value), bs.value
 
 
@@ -199,6 +213,22 @@ def kg_get_u(plan, n, out=None, complex_field=False):
     p, d = _buf(out)
     _check(_lib.kg_get_u(plan, p, d), plan)
     return out
+
+
+def kg_get_state(plan, n, u_prev=None, u_cur=None, complex_field=False, want_prev=True):
+    """(u^{n-1}, u^n) in physical space; outputs are allocated on the host
+    when not given (u^{n-1} is None when want_prev is false)."""
+    dt = np.complex128 if complex_field else np.float64
+    if u_prev is None and want_prev:
+        u_prev = np.empty((n, n, n), dt)
+    if u_cur is None:
+        u_cur = np.empty((n, n, n), dt)
+    pp, dp = _buf(u_prev)
+    pc, dc = _buf(u_cur)
+    if u_prev is not None and dp != dc:
+        raise ValueError("u_prev and u_cur must both be host or both be device arrays")
+    _check(_lib.kg_get_state(plan, pp, pc, dc), plan)
+    return u_prev, u_cur
 
 
 def kg_get_spectrum(plan, n, which=0, out=None, complex_field=False):

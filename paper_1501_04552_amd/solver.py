@@ -70,8 +70,15 @@ class Solver:
     def records(self, first, count):
         return _kg.kg_records(self.plan, first, count)
 
-    def stats(self):
-        return _kg.kg_stats(self.plan)
+    def energies(self, first, count):
+        return _kg.kg_energies(self.plan, first, count)
+
+    def stats(self, max_abs_u=False):
+        return _kg.kg_stats(self.plan, max_abs_u)
+
+    def state(self):
+        """(u^{n-1}, u^n) on the host."""
+        return _kg.kg_get_state(self.plan, self.n, complex_field=self.complex_field)
 
     def u(self, out=None):
         return _kg.kg_get_u(self.plan, self.n, out, self.complex_field)

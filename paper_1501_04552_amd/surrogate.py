@@ -151,6 +151,28 @@ def evaluate(model, X, blown, tb, solver_seconds, n=64, dt=0.005, max_steps=2000
     }
 
 
+def amortised(res, label_seconds, train_seconds):
+    """What the surrogate costs to build (labelling its training sweep with
+    the solver, then training) against what it saves per query: the number
+    of queries after which answering with the surrogate (and rerunning the
+    deferred ones) has paid for building it, and the speedup over the solver
+    alone at the held-out set's size once the building cost is included.
+    The per-query figures of `evaluate` leave the building cost out."""
+    nq = res["queries"]
+    t = res["seconds"]
+    per_solver = t["solver_all"] / nq
+    per_surrogate = (t["inference"] + t["solver_deferred"]) / nq
+    build = label_seconds + train_seconds
+    saving = per_solver - per_surrogate
+    return {"build_seconds": build, "label_seconds": label_seconds,
+            "train_seconds": train_seconds,
+            "solver_seconds_per_query": per_solver,
+            "surrogate_seconds_per_query": per_surrogate,
+            "break_even_queries": build / saving if saving > 0 else None,
+            "speedup_incl_build_at_held_out_size":
+                t["solver_all"] / (build + t["inference"] + t["solver_deferred"])}
+
+
 def main(argv=None):
     """Full pipeline: label a training sweep and a held-out sweep with the
     solver, train the MLP, evaluate it with solver fallback; prints JSON."""
@@ -170,10 +192,12 @@ def main(argv=None):
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--save", default=None, help="write the labelled sweeps to this .npz")
+    ap.add_argument("--quiet", action="store_true", help="no progress and no JSON output")
     args = ap.parse_args(argv)
 
     def log(msg):
-        print(msg, file=sys.stderr, flush=True)
+        if not args.quiet:
+            print(msg, file=sys.stderr, flush=True)
 
     cfg = dict(n=args.n, dt=args.dt, max_steps=args.max_steps, threshold=1e3)
     Xtr = ki.surrogate_params(args.train, seed=1)
@@ -190,6 +214,7 @@ def main(argv=None):
                               seed=0, log=log)
     res = evaluate(model, Xte, bte, tte, s_te, **cfg)
     model.close()
+    res["amortised"] = amortised(res, s_tr, t_train)
     res.update({"workload": f"train {args.train} runs (seed 1), held out {args.test} (seed 2), "
                             f"{args.n}^3, dt={args.dt}, <= {args.max_steps} steps, blow-up at "
                             "max|u| > 1e3; MLP 4-128-128-2 GELU FP32, Adam lr "
@@ -197,7 +222,8 @@ def main(argv=None):
                 "blown_fraction_train": float(btr.mean()), "blown_fraction_test": float(bte.mean()),
                 "label_seconds_train": s_tr, "train_seconds": t_train,
                 "loss_first_last": [hist[0], hist[-1]]})
-    print(json.dumps(res), flush=True)
+    if not args.quiet:
+        print(json.dumps(res), flush=True)
     return res
 
 

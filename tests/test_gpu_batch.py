@@ -24,7 +24,15 @@ RUNS = [
     dict(n=64, A=1.5, sigma=(0.7, 1.4, 1.1), dt=0.005, max_steps=150, threshold=1e3),
     dict(n=32, A=4.0, sigma=(1.6, 1.3, 1.8), dt=0.005, max_steps=300, threshold=1e3),
     dict(n=48, A=0.6, sigma=(0.5, 0.6, 0.7), dt=0.005, max_steps=90, threshold=1e3),
+    # the sweep's large classes (most of its kernel time): one blow-up and one
+    # finished run each
+    dict(n=96, A=3.0, sigma=(1.2, 0.9, 1.5), dt=0.005, max_steps=400, threshold=1e3),
+    dict(n=96, A=1.0, sigma=(0.8, 1.3, 1.0), dt=0.005, max_steps=200, threshold=1e3),
+    dict(n=128, A=3.5, sigma=(1.0, 1.4, 1.1), dt=0.005, max_steps=300, threshold=1e3),
+    dict(n=128, A=1.4, sigma=(1.1, 0.7, 0.9), dt=0.005, max_steps=150, threshold=1e3),
 ]
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "batch_cases.json")
 
 
 def single(kg, r):
@@ -86,6 +94,39 @@ def test_batch_oracle_parity(kg):
         else:
             E = ref["energy"][r["max_steps"]]
             assert abs(b["E_final"] - E) <= 1e-11 * abs(E)
+
+
+def test_batch_large_sizes_match_oracle(kg):
+    """96^3 and 128^3 runs (radix-3 and power-of-two plans of the sweep's
+    largest classes) against the oracle's runs (tests/golden/batch_cases.json,
+    written by tests/golden/make_full_size.py from oracle/ only): blow-up
+    level exact; E^{-1/2}, the final energy and max|u| to 1e-11 relative.
+    For a blown run max|u| is taken at the blown level b, where the run
+    amplifies perturbations: the reference file holds the oracle's response
+    to data scaled by 1 + 1e-13, i.e. the amplification kappa of a relative
+    perturbation.  The two sides differ by rounding of ~1e-15 per level,
+    accumulating like a random walk over the b levels and amplified by at
+    most kappa, so max|u| is held to 10 kappa 1e-15 sqrt(b) when that exceeds
+    1e-11."""
+    cases = json.load(open(GOLDEN))["cases"]
+    runs = [dict(n=c["n"], A=c["A"], sigma=tuple(c["sigma"]), dt=c["dt"],
+                 max_steps=c["max_steps"], threshold=c["threshold"]) for c in cases]
+    res, _ = kg.kg_batch_run(runs)
+    assert any(b["blew_up"] for b in res) and not all(b["blew_up"] for b in res)
+    for c, b in zip(cases, res):
+        ref, pert = c["ref"], c["perturbed_1e13"]
+        assert b["blew_up"] == (ref["blowup_step"] >= 0)
+        assert abs(b["E0"] - ref["E0"]) <= 1e-11 * abs(ref["E0"])
+        kappa = abs(pert["max_abs_u"] - ref["max_abs_u"]) / ref["max_abs_u"] / 1e-13
+        levels = ref["blowup_step"] if ref["blowup_step"] >= 0 else c["max_steps"]
+        tol_max = max(1e-11, 10 * kappa * 1e-15 * np.sqrt(levels))
+        assert abs(b["max_abs_u"] - ref["max_abs_u"]) <= tol_max * ref["max_abs_u"], (c, b)
+        if b["blew_up"]:
+            assert b["steps_done"] == ref["blowup_step"]
+            assert abs(b["t_blowup"] - ref["blowup_step"] * c["dt"]) < 1e-12
+        else:
+            assert b["steps_done"] == c["max_steps"]
+            assert abs(b["E_final"] - ref["E_final"]) <= 1e-11 * abs(ref["E_final"])
 
 
 def test_batch_sweep_sizes_and_autotuner(kg, tmp_path):

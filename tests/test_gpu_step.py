@@ -177,7 +177,8 @@ def test_slab_chain_is_bitwise_independent_of_slab_count(kg, monkeypatch, precis
     line sees the same arithmetic, so one slab, the default slabs and many
     ragged slabs, on either schedule, agree bitwise (384^3: 2 default slabs in
     FP64; 10 slabs of 40 planes, the last of 24).  Eight steps replay a graph,
-    the rest run eagerly, around an energy() call that rebuilds the field."""
+    the rest single-step graphs, around an energy() call that rebuilds the
+    field."""
     n, dt = 384, 0.005
     u0 = ki.gaussian(n, 1.2, (0.8, 1.0, 1.3))
     out = {}
@@ -234,23 +235,128 @@ def test_uniform_recurrence_at_512(kg):
     assert abs(u[0, 0, 0] - ref["u"][0, 0, 0]) <= 1e-12 * abs(ref["u"][0, 0, 0])
 
 
-def test_graph_replays_match_single_step_launches(kg):
-    """Runs of >= 8 steps replay captured graphs; single steps launch eagerly.
-    Both paths must give the same bits, across several replays with eager work
-    and synchronisation in between."""
+def test_graph_replays_match_eager_launches(kg):
+    """Steps replay captured graphs (8-step and single-step ones); timed steps
+    launch every kernel eagerly.  All three must give the same bits, across
+    several replays with eager work and synchronisation in between."""
     n, dt = 32, 0.01
     u0 = ki.gaussian(n, 1.5, (0.9, 1.1, 1.3))
-    with kg.Solver(n, dt) as a, kg.Solver(n, dt) as b:
-        a.set_state(u0)
-        b.set_state(u0)
+    with kg.Solver(n, dt) as a, kg.Solver(n, dt) as b, kg.Solver(n, dt) as c:
+        for s in (a, b, c):
+            s.set_state(u0)
         for rep in range(3):
             for _ in range(16):
                 a.step(1)
             b.step(16)
-            assert a.stats()[0] == b.stats()[0] == 16 * (rep + 1)
-            assert np.array_equal(a.u(), b.u())
-            assert a.energy() == b.energy()
+            kg.kg_step(c.plan, 16, kg.KG_STEP_TIMED)
+            assert a.stats()[0] == b.stats()[0] == c.stats()[0] == 16 * (rep + 1)
+            assert np.array_equal(a.u(), b.u()) and np.array_equal(a.u(), c.u())
+            assert a.energy() == b.energy() == c.energy()
         assert np.array_equal(a.records(0, 48)[0], b.records(0, 48)[0])
+        assert np.array_equal(a.records(0, 48)[0], c.records(0, 48)[0])
+
+
+def test_energy_series_and_max_abs_u_match_oracle(kg):
+    """kg_energies gives E^{m-1/2} at every level 0..n (the oracle's energy
+    array), kg_stats the newest level's max|u|."""
+    n, dt, steps = 32, 0.01, 100
+    u0 = ki.gaussian(n, 1.3, (0.9, 1.1, 1.3))
+    ref = oracle.run(u0, dt, steps)
+    with kg.Solver(n, dt) as s:
+        s.set_state(u0)
+        E0 = s.energies(0, 1)
+        assert abs(E0[0] - ref["energy"][0]) <= 1e-12 * abs(ref["energy"][0])
+        _, _, _, mx0 = s.stats(max_abs_u=True)
+        assert abs(mx0 - ref["maxu"][0]) <= 1e-12 * ref["maxu"][0]
+        s.step(steps)
+        E = s.energies(0, steps + 1)
+        _, _, _, mx = s.stats(max_abs_u=True)
+        E_mid = s.energies(40, 21)
+        assert s.energy()[0] == E[-1]
+        with pytest.raises(kg.KGError) as e:
+            s.energies(0, steps + 2)
+        assert e.value.status == kg.KG_E_INVALID
+    assert np.abs(E - ref["energy"]).max() <= 1e-11 * np.abs(ref["energy"]).max()
+    assert np.array_equal(E_mid, E[40:61])
+    assert abs(mx - ref["maxu"][steps]) <= 1e-11 * ref["maxu"][steps]
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_levels_after_a_blowup(kg, precision):
+    """After a blow-up at level b the blown step has overwritten the level
+    before it: kg_get_spectrum(which=1) and kg_get_state's u_prev refuse;
+    u^b itself, the energies up to E^{b-1/2} and max|u^b| stay available and
+    match the oracle.
+
+    Tolerance at the blown level: the run amplifies a relative perturbation
+    of its data by kappa there (measured below with the oracle, data scaled
+    by 1 + 1e-13); rounding of ~1e-15 per level accumulates like a random
+    walk over the b levels, so u^b is held to 10 kappa 1e-15 sqrt(b).  FP32
+    keeps (v, v - v_prev) and rebuilds u^b as v^{b+1} - (v^{b+1} - v^b) in
+    float, whose rounding is that of v^{b+1}, many times u^b one step past
+    the blow-up: the blown level is then only checked against the record of
+    max|u^b| the step itself took, to the FP32 target 1e-4."""
+    dt = 0.01
+    ref = oracle.run(ki.uniform(8, 1.5), dt, 300, threshold=1e3)
+    pert = oracle.run(ki.uniform(8, 1.5 * (1 + 1e-13)), dt, 300, threshold=1e3)
+    b = ref["blowup_step"]
+    kappa = abs(pert["u"].max() - ref["u"].max()) / ref["u"].max() / 1e-13
+    tol_b = max(1e-11, 10 * kappa * 1e-15 * np.sqrt(b))
+    with kg.Solver(8, dt, blowup_threshold=1e3, precision=precision) as s:
+        s.set_state(ki.uniform(8, 1.5))
+        st, done = s.step(300)
+        assert st == kg.KG_BLOWUP and abs(done - b) <= precision
+        for call in (lambda: s.spectrum(1), lambda: s.state()):
+            with pytest.raises(kg.KGError) as e:
+                call()
+            assert e.value.status == kg.KG_E_INVALID
+        _, ub = kg.kg_get_state(s.plan, 8, want_prev=False)
+        E = s.energies(0, done + 1)
+        steps, blown, bstep, mx = s.stats(max_abs_u=True)
+    assert (steps, blown, bstep) == (done, True, done)
+    if precision == 1:
+        # FP32 may also cross the threshold one level apart from the oracle
+        assert abs(mx - np.abs(ub).max()) <= 1e-4 * mx
+        return
+    assert abs(mx - np.abs(ub).max()) <= 1e-12 * mx
+    assert np.abs(ub - ref["u"]).max() <= tol_b * np.abs(ref["u"]).max()
+    assert abs(mx - ref["maxu"][b]) <= tol_b * ref["maxu"][b]
+    # E is a difference of terms growing like u^4: compare it where max|u| < 3
+    # (its terms below ~100 |E|), and its presence up to E^{b-1/2}
+    keep = np.flatnonzero(ref["maxu"][:b + 1] < 3.0)
+    assert len(keep) > 50 and np.all(np.isfinite(E))
+    dE = np.abs(E[keep] - ref["energy"][keep]) / np.abs(ref["energy"][keep])
+    assert dE.max() <= 1e-11
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_two_level_restore_from_get_state(kg, precision):
+    """(u^{n-1}, u^n) from kg_get_state restart the run with the two-level
+    start: the continuation equals the uninterrupted run up to the rounding
+    of one transform pair per level.  FP64: a c2r/r2c round trip rounds at
+    ~2 log2(M) eps ~ 3e-15 relative, which the 40 further nonlinear steps may
+    grow a few times: 3e-14.  FP32 keeps (v, v - v_prev) in float; the
+    restart forms v - v_prev from two separately rounded levels, an error
+    of eps32 |v| on a difference of size omega dt |v|, so the continuation
+    is good to ~eps32 / (omega dt) ~ 1e-5: held to the FP32 target 1e-4."""
+    n, dt = 32, 0.01
+    u0 = ki.gaussian(n, 0.9, (0.9, 1.1, 1.3))
+    with kg.Solver(n, dt, precision=precision) as a, kg.Solver(n, dt, precision=precision) as b:
+        a.set_state(u0)
+        a.step(60)
+        up, uc = a.state()
+        assert np.array_equal(uc, a.u())
+        b.set_state(uc, up, kg.KG_INIT_TWO_LEVEL)
+        Ea, Eb = a.energy()[0], b.energy()[0]
+        a.step(40)
+        b.step(40)
+        ua, ub = a.u(), b.u()
+    tol = 3e-14 if precision == 0 else 1e-4
+    assert abs(Ea - Eb) <= tol * abs(Ea)
+    assert rel_l2(ub, ua) <= tol
+    if precision == 0:
+        ref = oracle.run(u0, dt, 100)
+        assert rel_l2(ub, ref["u"]) <= 1e-11
 
 
 def test_stepping_after_a_blowup_and_argument_checks(kg):
