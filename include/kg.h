@@ -315,6 +315,34 @@ kg_status kg_mlp_grad(kg_mlp_t *m, const float *d_x, const float *d_y, int B, fl
 kg_status kg_mlp_train_step(kg_mlp_t *m, const float *d_x, const float *d_y, int B, float lr,
                             float *host_loss);
 
+/*
+ * Surrogate inference for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the outputs of kg_mlp_forward for n inputs, computed by the
+ * same kernels, bit for bit, without a kg_mlp_t and without any allocation.
+ *   hidden:   width of the two hidden layers, 1 .. KG_MLP_NOALLOC_MAX_HIDDEN;
+ *   d_params: device array of kg_mlp_num_params(hidden) floats in the flat
+ *             layout of kg_mlp_get_params (caller-owned, only read);
+ *   mean, stdev: host arrays of 4 floats (stdev > 0) standardising the
+ *             inputs as kg_mlp_set_norm does; NULL means 0 / 1;
+ *   d_x, d_out: device arrays, n x 4 inputs and n x 2 outputs (any n >= 0;
+ *             n = 0 is a no-op and they may then be NULL).
+ * Work is enqueued on hip_stream and the call returns without waiting.
+ * The hidden activations live in a fixed scratch array of
+ * KG_MLP_NOALLOC_SCRATCH_BYTES in the library's device code, one per GPU,
+ * held until the process ends; inputs are processed in chunks of
+ * floor(KG_MLP_NOALLOC_SCRATCH_BYTES / (4 (4 + 2 hidden))) rows.  Every call
+ * on a GPU shares that GPU's array: calls that overlap on one GPU (other
+ * streams, other threads) race and must be serialised by the caller.
+ * Errors: KG_E_INVALID (NULL d_params, NULL d_x / d_out with n > 0, n < 0,
+ * hidden out of range, stdev <= 0), KG_E_HIP (launch failure).
+ */
+#define KG_MLP_NOALLOC_MAX_HIDDEN 1024
+#define KG_MLP_NOALLOC_SCRATCH_BYTES (4u << 20)
+kg_status kg_mlp_forward_noalloc(int hidden, const float *d_params, const float *mean,
+                                 const float *stdev, const float *d_x, int n, float *d_out,
+                                 void *hip_stream);
+
 /* ------------------------------------------------------------------------ */
 /* Test and measurement hooks (not needed to run the solver).               */
 /* ------------------------------------------------------------------------ */

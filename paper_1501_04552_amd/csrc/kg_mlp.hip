@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -32,13 +33,18 @@ __device__ __forceinline__ float gelu_grad(float x)
            x * expf(-0.5f * x * x) * 0.39894228040143268f;
 }
 
+// Input standardisation, passed by value to the kernels.
+struct Norm {
+    float mean[NIN], stdev[NIN];
+};
+
 // xs = (x - mean) / std
-__global__ void k_standardize(const float *x, const float *norm, float *xs, int B)
+__global__ void k_standardize(const float *x, Norm norm, float *xs, int B)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= B * NIN) return;
     const int c = i % NIN;
-    xs[i] = (x[i] - norm[c]) / norm[NIN + c];
+    xs[i] = (x[i] - norm.mean[c]) / norm.stdev[c];
 }
 
 // z[b][o] = sum_i in[b][i] W[o][i] + bias[o]; a = GELU(z) when act.
@@ -139,7 +145,8 @@ struct kg_mlp_s {
     size_t np = 0;
     hipStream_t st = nullptr;
     void *mem = nullptr;
-    float *p = nullptr, *g = nullptr, *m = nullptr, *v = nullptr, *norm = nullptr;
+    Norm norm{{0, 0, 0, 0}, {1, 1, 1, 1}};
+    float *p = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;
     float *xs = nullptr, *z1 = nullptr, *a1 = nullptr, *z2 = nullptr, *a2 = nullptr, *out = nullptr,
           *dout = nullptr, *dz2 = nullptr, *dz1 = nullptr, *loss = nullptr;
     long t = 0;  // Adam steps taken
@@ -174,16 +181,55 @@ kg_status mfail(kg_mlp_s *m, kg_status s, const std::string &msg)
                                                                hipGetErrorString(e_));        \
     } while (0)
 
+// The three layers for B standardised rows xs: parameters p (flat layout),
+// pre-activations z1, z2 and activations a1, a2 (z may alias a when only the
+// output is wanted), outputs out.
+void layers(hipStream_t st, int H, const float *p, const float *xs, float *z1, float *a1, float *z2,
+            float *a2, float *out, int B)
+{
+    const float *W1 = p, *b1 = W1 + (size_t)H * NIN, *W2 = b1 + H, *b2 = W2 + (size_t)H * H,
+                *W3 = b2 + H, *b3 = W3 + (size_t)NOUT * H;
+    hipLaunchKernelGGL(k_linear_fwd, dim3(blocks((long)B * H)), dim3(256), 0, st, xs, W1, b1, z1, a1,
+                       B, NIN, H, 1);
+    hipLaunchKernelGGL(k_linear_fwd, dim3(blocks((long)B * H)), dim3(256), 0, st, a1, W2, b2, z2, a2,
+                       B, H, H, 1);
+    hipLaunchKernelGGL(k_linear_fwd, dim3(blocks((long)B * NOUT)), dim3(256), 0, st, a2, W3, b3, out,
+                       out, B, H, NOUT, 0);
+}
+
 // Forward of B <= maxB standardised rows already in m->xs.
 void forward(kg_mlp_s *m, int B)
 {
-    const int H = m->H;
-    hipLaunchKernelGGL(k_linear_fwd, dim3(blocks((long)B * H)), dim3(256), 0, m->st, m->xs, m->W1(),
-                       m->b1(), m->z1, m->a1, B, NIN, H, 1);
-    hipLaunchKernelGGL(k_linear_fwd, dim3(blocks((long)B * H)), dim3(256), 0, m->st, m->a1, m->W2(),
-                       m->b2(), m->z2, m->a2, B, H, H, 1);
-    hipLaunchKernelGGL(k_linear_fwd, dim3(blocks((long)B * NOUT)), dim3(256), 0, m->st, m->a2, m->W3(),
-                       m->b3(), m->out, m->out, B, H, NOUT, 0);
+    layers(m->st, m->H, m->p, m->xs, m->z1, m->a1, m->z2, m->a2, m->out, B);
+}
+
+// Scratch of kg_mlp_forward_noalloc: the standardised inputs and both hidden
+// activations of one chunk of rows.  Each GPU holds its own copy; host code
+// uses only the per-device addresses from hipGetSymbolAddress.
+constexpr size_t NOALLOC_SCRATCH_FLOATS = KG_MLP_NOALLOC_SCRATCH_BYTES / sizeof(float);
+static __device__ __align__(256) float scratch[NOALLOC_SCRATCH_FLOATS];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+float *scratch_ptr[MAX_DEVICES] = {};
+
+// Device address of `scratch` on the current device, looked up once per
+// device (on that device's first call).
+hipError_t scratch_address(float **out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        scratch_ptr[dev] = (float *)p;
+    }
+    *out = scratch_ptr[dev];
+    return hipSuccess;
 }
 
 void backward(kg_mlp_s *m, const float *d_y, int B)
@@ -224,7 +270,7 @@ kg_status kg_mlp_create(int hidden, int max_batch, const float *init_params, voi
     m->np = kg_mlp_num_params(hidden);
     m->st = (hipStream_t)hip_stream;
     const size_t B = max_batch, H = hidden;
-    const size_t nfl = 4 * m->np + 2 * NIN + B * NIN + 4 * B * H + 2 * B * NOUT + 2 * B * H + 1;
+    const size_t nfl = 4 * m->np + B * NIN + 4 * B * H + 2 * B * NOUT + 2 * B * H + 1;
     if (hipMalloc(&m->mem, nfl * sizeof(float)) != hipSuccess) {
         delete m;
         return KG_E_NOMEM;
@@ -234,7 +280,6 @@ kg_status kg_mlp_create(int hidden, int max_batch, const float *init_params, voi
     m->g = c; c += m->np;
     m->m = c; c += m->np;
     m->v = c; c += m->np;
-    m->norm = c; c += 2 * NIN;
     m->xs = c; c += B * NIN;
     m->z1 = c; c += B * H;
     m->a1 = c; c += B * H;
@@ -245,12 +290,10 @@ kg_status kg_mlp_create(int hidden, int max_batch, const float *init_params, voi
     m->dz2 = c; c += B * H;
     m->dz1 = c; c += B * H;
     m->loss = c;
-    std::vector<float> zeros(2 * m->np, 0.0f), norm0 = {0, 0, 0, 0, 1, 1, 1, 1};
+    std::vector<float> zeros(2 * m->np, 0.0f);
     hipError_t e = hipMemcpyAsync(m->p, init_params, m->np * sizeof(float), hipMemcpyHostToDevice, m->st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(m->m, zeros.data(), 2 * m->np * sizeof(float), hipMemcpyHostToDevice, m->st);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(m->norm, norm0.data(), 2 * NIN * sizeof(float), hipMemcpyHostToDevice, m->st);
     if (e == hipSuccess) e = hipStreamSynchronize(m->st);
     if (e != hipSuccess) {
         kg_mlp_destroy(m);
@@ -272,14 +315,12 @@ const char *kg_mlp_last_error(const kg_mlp_t *m) { return m ? m->err.c_str() : "
 kg_status kg_mlp_set_norm(kg_mlp_t *m, const float *mean, const float *stdev)
 {
     if (!m || !mean || !stdev) return KG_E_INVALID;
-    float h[2 * NIN];
-    for (int i = 0; i < NIN; ++i) {
+    for (int i = 0; i < NIN; ++i)
         if (!(stdev[i] > 0)) return mfail(m, KG_E_INVALID, "standard deviations must be > 0");
-        h[i] = mean[i];
-        h[NIN + i] = stdev[i];
+    for (int i = 0; i < NIN; ++i) {
+        m->norm.mean[i] = mean[i];
+        m->norm.stdev[i] = stdev[i];
     }
-    MCHK(m, hipMemcpyAsync(m->norm, h, sizeof h, hipMemcpyHostToDevice, m->st));
-    MCHK(m, hipStreamSynchronize(m->st));
     return KG_OK;
 }
 
@@ -304,6 +345,38 @@ kg_status kg_mlp_forward(kg_mlp_t *m, const float *d_x, int n, float *d_out)
     }
     MCHK(m, hipGetLastError());
     return KG_OK;
+}
+
+kg_status kg_mlp_forward_noalloc(int hidden, const float *d_params, const float *mean,
+                                 const float *stdev, const float *d_x, int n, float *d_out,
+                                 void *hip_stream)
+{
+    if (!d_params || n < 0 || (n > 0 && (!d_x || !d_out))) return KG_E_INVALID;
+    if (hidden < 1 || hidden > KG_MLP_NOALLOC_MAX_HIDDEN) return KG_E_INVALID;
+    Norm norm{{0, 0, 0, 0}, {1, 1, 1, 1}};
+    for (int i = 0; i < NIN; ++i) {
+        if (mean) norm.mean[i] = mean[i];
+        if (stdev) {
+            if (!(stdev[i] > 0)) return KG_E_INVALID;
+            norm.stdev[i] = stdev[i];
+        }
+    }
+    float *sc = nullptr;
+    if (scratch_address(&sc) != hipSuccess) return KG_E_HIP;
+    // rows per chunk: standardised inputs and two activation rows each
+    const size_t per_row = NIN + 2 * (size_t)hidden;
+    const int chunk = (int)(NOALLOC_SCRATCH_FLOATS / per_row);
+    hipStream_t st = (hipStream_t)hip_stream;
+    float *xs = sc, *a1 = xs + (size_t)chunk * NIN, *a2 = a1 + (size_t)chunk * hidden;
+    for (int s = 0; s < n; s += chunk) {
+        const int B = n - s < chunk ? n - s : chunk;
+        hipLaunchKernelGGL(k_standardize, dim3(blocks((long)B * NIN)), dim3(256), 0, st,
+                           d_x + (long)s * NIN, norm, xs, B);
+        // pre-activations are not kept: z aliases a; the last layer writes
+        // straight into the caller's output
+        layers(st, hidden, d_params, xs, a1, a1, a2, a2, d_out + (long)s * NOUT, B);
+    }
+    return hipGetLastError() == hipSuccess ? KG_OK : KG_E_HIP;
 }
 
 kg_status kg_mlp_grad(kg_mlp_t *m, const float *d_x, const float *d_y, int B, float *host_loss,

@@ -99,6 +99,8 @@ _SIGS = {
     "kg_mlp_forward": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp]),
     "kg_mlp_grad": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp, _vp]),
     "kg_mlp_train_step": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, ctypes.c_float, _vp]),
+    "kg_mlp_forward_noalloc": (ctypes.c_int, [ctypes.c_int, _vp, _vp, _vp, _vp, ctypes.c_int, _vp,
+                                              _vp]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -374,3 +376,16 @@ def kg_mlp_train_step(m, x_dev, y_dev, lr, want_loss=False):
     _mcheck(_lib.kg_mlp_train_step(m, x_dev.data_ptr(), y_dev.data_ptr(), x_dev.shape[0],
                                    ctypes.c_float(lr), loss.ctypes.data if want_loss else None), m)
     return float(loss[0]) if want_loss else None
+
+
+def kg_mlp_forward_noalloc(hidden, params_dev, x_dev, out_dev, mean=None, stdev=None, stream=None):
+    """Outputs for x_dev [n, 4] into out_dev [n, 2] (float32 cuda tensors)
+    from parameters in the device tensor params_dev; allocates nothing."""
+    m = None if mean is None else np.ascontiguousarray(mean, np.float32)
+    s = None if stdev is None else np.ascontiguousarray(stdev, np.float32)
+    st = _lib.kg_mlp_forward_noalloc(hidden, params_dev.data_ptr(),
+                                     None if m is None else m.ctypes.data,
+                                     None if s is None else s.ctypes.data,
+                                     x_dev.data_ptr(), x_dev.shape[0], out_dev.data_ptr(), stream)
+    if st != KG_OK:
+        raise KGError(st, "kg_mlp_forward_noalloc")
