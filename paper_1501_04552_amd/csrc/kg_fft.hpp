@@ -203,9 +203,29 @@ struct Radix {
 // (SH = 0: none), so the strided writes of the early stages spread over the
 // LDS banks.  The y and z passes interleave W lines per slot and use SH = 3.
 template <int SH = 3>
-__device__ __forceinline__ int lpos(int p) { return SH ? p + (p >> SH) : p; }
+__device__ __forceinline__ int lpos(int p) { return SH > 0 ? p + (p >> SH) : p; }
 template <int NL, int SH = 3>
-constexpr int lslots() { return SH ? NL + NL / (1 << SH) : NL; }
+constexpr int lslots() { return SH > 0 ? NL + NL / (1 << SH) : NL; }
+
+// SH = SWZ: no padding; instead bits 0-2 of a position are XORed with bits
+// 3-5 and bit 3 with bit 6, a bijection on every aligned block of 128
+// positions.  LDS serves the lanes of a wavefront in groups of 128 bytes
+// (8 lanes of 16-byte values, 16 lanes of 8-byte ones); within such a group
+// the strided stage writes of a contiguous radix-8 line (positions 8t + s,
+// and 64(t/8) + 8s + t%8) then hit distinct banks, and the contiguous reads
+// t + j*TPL stay a permutation of one bank row.  It needs no LDS beyond the
+// line and less index arithmetic than padding.
+constexpr int SWZ = -1;
+template <int NL, int SH>
+__device__ __forceinline__ int lslot(int p)
+{
+    if constexpr (SH == SWZ) {
+        static_assert(NL % 128 == 0, "the swizzle permutes whole blocks of 128 positions");
+        return p ^ ((p >> 3) & 7) ^ (((p >> 6) & 1) << 3);
+    } else {
+        return lpos<SH>(p);
+    }
+}
 
 // Synchronisation between the stages of one line: the whole workgroup
 // (lines spread over several waves) or one wave (every thread of the line,
@@ -292,7 +312,7 @@ __device__ __forceinline__ void fft_line(cx<T> (&v)[Radix<NL>::E], cx<T> *lds, i
     if constexpr (S > 0) {
         stage_sync<SY>();
 #pragma unroll
-        for (int j = 0; j < E; ++j) v[j] = lds[lpos<SH>(t + j * TPL) * ls];
+        for (int j = 0; j < E; ++j) v[j] = lds[lslot<NL, SH>(t + j * TPL) * ls];
         if constexpr (!last) stage_sync<SY>();
     }
 #pragma unroll
@@ -329,7 +349,7 @@ __device__ __forceinline__ void fft_line(cx<T> (&v)[Radix<NL>::E], cx<T> *lds, i
         } else {
             const int base = (i / L) * L * R + k;
 #pragma unroll
-            for (int s = 0; s < R; ++s) lds[lpos<SH>(base + s * L) * ls] = x[s];
+            for (int s = 0; s < R; ++s) lds[lslot<NL, SH>(base + s * L) * ls] = x[s];
         }
     }
     if constexpr (!last) fft_line<T, NL, DIR, SY, SH, S + 1>(v, lds, ls, t, tw, twm, pre);

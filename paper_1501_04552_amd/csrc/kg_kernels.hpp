@@ -129,11 +129,16 @@ struct XCfg {
     static constexpr int TPL = Radix<N>::TPL;
     static constexpr int NT = 256;
     static constexpr int PPB = NT / TPL;  // line pairs per workgroup
-    // LDS pad spacing of the contiguous lines: one slot per 8 positions in
-    // FP64 (fewest bank conflicts), none in FP32, where the padding's index
-    // arithmetic costs more registers (82 vs 64 VGPRs: 5 vs 8 waves per
-    // SIMD) than its conflicts cost time (measured at 512^3).
-    static constexpr int SH = sizeof(T) == 8 ? 3 : 0;
+    // LDS slots of the contiguous lines.  FP64: the XOR swizzle on 2^a lines
+    // of >= 256 points (bank conflicts 0.03 of LDS cycles against 0.21 with
+    // padding at 512^3, less LDS and fewer registers, same time), else one pad
+    // slot per 8 positions.  FP32: plain slots; padding (82 VGPRs) and the
+    // swizzle (78 VGPRs: its XORed addresses cannot use immediate offsets) both
+    // cost occupancy (5-6 instead of 8 waves per SIMD) that the conflicts (0.40
+    // of LDS cycles, 0.02 with the swizzle) do not repay: 0.245 ms plain
+    // against 0.265 swizzled, 0.39 with the swizzle forced to 8 waves (spills).
+    static constexpr bool SWZ_OK = sizeof(T) == 8 && !Radix<N>::THREE && N >= 256;
+    static constexpr int SH = SWZ_OK ? SWZ : (sizeof(T) == 8 ? 3 : 0);
     static constexpr int RS = lslots<N, SH>();
     static constexpr long blocks() { return ((long)N * N / 2 + PPB - 1) / PPB; }
     // complex fields: one line per row, PPB rows per workgroup
@@ -261,7 +266,7 @@ __device__ __forceinline__ void xbody(const XArgs<T> &a, long blk, cx<T> *rows, 
 #pragma unroll
     for (int j = 0; j < E; ++j) {
         const int k = t + j * TPL;
-        if (k >= NH) r[lpos<C::SH>(k)] = v[j];
+        if (k >= NH) r[lslot<N, C::SH>(k)] = v[j];
     }
     stage_sync<XSY>();
     if (act) {
@@ -271,7 +276,7 @@ __device__ __forceinline__ void xbody(const XArgs<T> &a, long blk, cx<T> *rows, 
             const int k = t + j * TPL;
             if (k <= NH) {
                 const cx<T> zk = v[j];
-                const cx<T> zm = k == 0 ? conjg(zk) : conjg(r[lpos<C::SH>(N - k)]);
+                const cx<T> zm = k == 0 ? conjg(zk) : conjg(r[lslot<N, C::SH>(N - k)]);
                 q1[k] = scale(zk + zm, (T)0.5);
                 q2[k] = scale(rot90<-1>(zk - zm), (T)0.5);
             }
