@@ -67,6 +67,8 @@ def sweep(args, kg, ki, torch):
     cache = os.environ.get("KG_TUNE_CACHE",
                            os.path.join(ROOT, "paper_1501_04552_amd", "tune_cache.json"))
     res, secs = kg.kg_batch_run(runs, tune=True, tune_cache=cache)
+    with open(cache) as f:
+        tuned = json.load(f)
     steps = sum(r["steps_done"] for r in res)
     sweep_bytes = sum(11 * r["n"] ** 2 * (r["n"] // 2 + 1) * 16 * o["steps_done"]
                       for r, o in zip(runs, res))
@@ -88,6 +90,8 @@ def sweep(args, kg, ki, torch):
             "seconds": secs, "runs_per_hour": len(runs) / secs * 3600.0,
             "run_steps_per_s": steps / secs, "blown_fraction": float(np.mean([o["blew_up"] for o in res])),
             "model_GBs": sweep_bytes / secs / 1e9,
+            "tuned": {k: v for k, v in sorted(tuned.items())
+                      if int(k.split("/")[1]) in ki.SWEEP_SIZES},
             "sequential_kg_step": {"runs": len(sample), "seconds_incl_setup": seq_secs,
                                    "runs_per_hour": len(sample) / seq_secs * 3600.0,
                                    "labels_agree": agree}}

@@ -90,17 +90,26 @@ void save_cache(const std::string &path, const std::map<std::string, int> &m)
     std::fclose(f);
 }
 
-std::string cache_key(int n) { return "fp64/" + std::to_string(n); }
+std::string cache_key(int n, const char *what) { return "fp64/" + std::to_string(n) + "/" + what; }
 
-// Fields per chunk of a size class (KG_BATCH_CHUNK_MB overrides; 0: the
-// whole class).  A graph replays all its steps on one chunk before the next,
-// the size classes running as concurrent branches.  On MI355X, for the
-// {48,64,96,128}^3 sweep, 400 MB chunks measured 17% faster than whole
-// classes; 50-200 MB lose to per-launch overheads, 800 MB and more to misses.
-double chunk_bytes()
+// Launch parameters of one grid size: tile width of the y and z passes,
+// persistent workgroups per CU (at most what the LDS allows), and fields
+// per chunk of the size class in MB (0: the whole class).  A graph replays
+// all its steps on one chunk before the next, the size classes running as
+// concurrent branches.  Defaults: on MI355X, for the {48,64,96,128}^3 sweep,
+// 400 MB chunks measured 17% faster than whole classes (50-200 MB lose to
+// per-launch overheads, 800 MB and more to cache misses).  The autotuner
+// replaces them per size; KG_BATCH_CHUNK_MB overrides the chunk size.
+struct Tune {
+    int W = 8;
+    int wpc = 4;
+    double chunk_mb = 400;
+};
+
+double chunk_bytes(const Tune &t)
 {
     if (const char *e = std::getenv("KG_BATCH_CHUNK_MB")) return std::atof(e) * 1e6;
-    return 400e6;
+    return t.chunk_mb * 1e6;
 }
 
 // ---------------------------------------------------------------------------
@@ -130,6 +139,7 @@ struct Launch {
 
 struct Class {
     int n = 0, W = 0;
+    Tune tune;
     const Launch *L = nullptr;
     std::vector<int> runs;            // run indices
     std::vector<BTask> xfull, yfull;  // full task lists (run-major)
@@ -209,11 +219,11 @@ struct Batch {
     std::vector<BRun> host;  // run table (host copy)
     std::vector<size_t> bytes;  // fields of each run (Q and both levels)
     int cus = 256, lds_cu = 160 * 1024;
-    // persistent grids: as many 256-thread workgroups as the LDS lets a CU
-    // hold (reductions add ~2 KB), at most 4 per CU, no more than the tasks
-    int grid(int lds, long tasks) const
+    // persistent grids: wpc 256-thread workgroups per CU, no more than the
+    // LDS lets a CU hold (reductions add ~2 KB), no more than the tasks
+    int grid(int lds, long tasks, int wpc) const
     {
-        const int per_cu = std::max(1, std::min(4, lds_cu / (lds + 2048)));
+        const int per_cu = std::max(1, std::min(wpc, lds_cu / (lds + 2048)));
         return (int)std::max(1L, std::min((long)per_cu * cus, tasks));
     }
     std::vector<Class> cls;
@@ -222,9 +232,15 @@ struct Batch {
     hipStream_t cap = nullptr;
     hipEvent_t fork = nullptr;
     hipGraphExec_t gexec = nullptr;
+    int *d_active = nullptr;        // active runs after the last replay (device)
+    int *h_active = nullptr;        // ... copied by each replay into pinned host memory
+    hipEvent_t done_ev[2] = {nullptr, nullptr};  // replays in flight
     ~Batch()
     {
         if (gexec) (void)hipGraphExecDestroy(gexec);
+        for (hipEvent_t e : done_ev)
+            if (e) (void)hipEventDestroy(e);
+        if (h_active) (void)hipHostFree(h_active);
         for (Class &c : cls) {
             if (c.side) (void)hipStreamDestroy(c.side);
             if (c.ev) (void)hipEventDestroy(c.ev);
@@ -235,7 +251,8 @@ struct Batch {
     }
 };
 
-kg_status setup(Batch &b, const kg_run_desc *runs, int nruns, const std::vector<int> &W, double L)
+kg_status setup(Batch &b, const kg_run_desc *runs, int nruns, const std::map<int, Tune> &tune,
+                double L)
 {
     b.nruns = nruns;
     b.host.assign(nruns, BRun{});
@@ -248,7 +265,7 @@ kg_status setup(Batch &b, const kg_run_desc *runs, int nruns, const std::vector<
         const kg_run_desc &d = runs[r];
         R.n = d.n;
         R.H = d.n / 2 + 1;
-        R.W = W[r];
+        R.W = tune.at(d.n).W;
         R.ntx = (R.H + R.W - 1) / R.W;
         R.P = ((R.ntx * R.W + 7) / 8) * 8;
         R.flag = d.max_steps > 0 ? 0 : 2;
@@ -290,6 +307,7 @@ kg_status setup(Batch &b, const kg_run_desc *runs, int nruns, const std::vector<
             b.cls.back().n = R.n;
             b.cls.back().W = R.W;
             b.cls.back().L = launch_table(R.n, R.W);
+            b.cls.back().tune = tune.at(d.n);
         }
         b.cls[cls_of[key]].runs.push_back(r);
     }
@@ -326,6 +344,8 @@ kg_status setup(Batch &b, const kg_run_desc *runs, int nruns, const std::vector<
     }
     const size_t o_runs = off;
     off += up(sizeof(BRun) * nruns);
+    const size_t o_active = off;
+    off += up(sizeof(int));
     hipError_t e = hipMalloc(&b.arena, off);
     if (e != hipSuccess) return bfail(KG_E_NOMEM, "batch arena of " + std::to_string(off) + " bytes");
     char *base = (char *)b.arena;
@@ -336,6 +356,10 @@ kg_status setup(Batch &b, const kg_run_desc *runs, int nruns, const std::vector<
         b.host[r].tw = base + tw_off[b.host[r].n];
     }
     b.d_runs = (BRun *)(base + o_runs);
+    b.d_active = (int *)(base + o_active);
+    BCHK(hipHostMalloc((void **)&b.h_active, sizeof(int), hipHostMallocDefault));
+    *b.h_active = nruns;
+    for (hipEvent_t &e : b.done_ev) BCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     int dev = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&b.cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -350,8 +374,8 @@ kg_status setup(Batch &b, const kg_run_desc *runs, int nruns, const std::vector<
         c.d_pc = (double *)(base + o_pc[k]);
         c.d_ccnt = (int *)(base + o_ccnt[k]);
         c.nlist = (int)c.runs.size();
-        c.gx = b.grid(c.L->x_lds, (long)c.xfull.size());
-        c.gyz = b.grid(c.L->yz_lds, (long)c.yfull.size());
+        c.gx = b.grid(c.L->x_lds, (long)c.xfull.size(), c.tune.wpc);
+        c.gyz = b.grid(c.L->yz_lds, (long)c.yfull.size(), c.tune.wpc);
         const int cnt[2] = {(int)c.xfull.size(), (int)c.yfull.size()};
         BCHK(hipMemcpyAsync(c.d_xt, c.xfull.data(), sizeof(BTask) * c.xfull.size(), hipMemcpyHostToDevice, b.st));
         BCHK(hipMemcpyAsync(c.d_yt, c.yfull.data(), sizeof(BTask) * c.yfull.size(), hipMemcpyHostToDevice, b.st));
@@ -444,6 +468,9 @@ kg_status make_graph(Batch &b, int G)
         BCHK(hipEventRecord(c.ev, c.side));
         BCHK(hipStreamWaitEvent(b.cap, c.ev, 0));
     }
+    // the replay ends by counting the active runs into pinned host memory
+    hipLaunchKernelGGL(kb_count_active, dim3(1), dim3(256), 0, b.cap, b.d_runs, b.nruns, b.d_active);
+    BCHK(hipMemcpyAsync(b.h_active, b.d_active, sizeof(int), hipMemcpyDeviceToHost, b.cap));
     BCHK(hipStreamEndCapture(b.cap, &g));
     hipError_t e = hipGraphInstantiate(&b.gexec, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
@@ -476,12 +503,12 @@ kg_status compact(Batch &b, int want, int &nsel)
         nsel += (int)list.size();
         // the finalize grid reads nlist; the full list stays allocated
         c.nlist = (int)list.size();
-        c.gx = b.grid(c.L->x_lds, (long)xt.size());
-        c.gyz = b.grid(c.L->yz_lds, (long)yt.size());
+        c.gx = b.grid(c.L->x_lds, (long)xt.size(), c.tune.wpc);
+        c.gyz = b.grid(c.L->yz_lds, (long)yt.size(), c.tune.wpc);
         // chunks of consecutive runs of about chunk_bytes() of fields each
         std::vector<int> ccnt;
         c.chunks.clear();
-        const double cap = chunk_bytes();
+        const double cap = chunk_bytes(c.tune);
         for (size_t a = 0; a < list.size();) {
             size_t e = a + 1;
             double acc = (double)b.bytes[list[a]];
@@ -494,7 +521,8 @@ kg_status compact(Batch &b, int want, int &nsel)
             ccnt.push_back(yb - ya);
             c.chunks.push_back(View{BList{c.d_xt + xa, c.d_ccnt + 2 * k}, BList{c.d_yt + ya, c.d_ccnt + 2 * k + 1},
                                     c.d_pa + 2 * xa, c.d_pc + 2 * ya, c.d_pa, c.d_pc, c.d_list + a,
-                                    (int)(e - a), b.grid(c.L->x_lds, xb - xa), b.grid(c.L->yz_lds, yb - ya)});
+                                    (int)(e - a), b.grid(c.L->x_lds, xb - xa, c.tune.wpc),
+                                    b.grid(c.L->yz_lds, yb - ya, c.tune.wpc)});
             a = e;
         }
         if (!ccnt.empty())
@@ -513,13 +541,13 @@ kg_status compact(Batch &b, int want, int &nsel)
     return KG_OK;
 }
 
-// Whole sweep of one batch; per-run tile widths W.
-kg_status run_batch(const kg_run_desc *runs, int nruns, const std::vector<int> &W, double L, int G,
-                    hipStream_t st, std::vector<BRun> &result, double *seconds)
+// Whole sweep of one batch with per-size launch parameters.
+kg_status run_batch(const kg_run_desc *runs, int nruns, const std::map<int, Tune> &tune, double L,
+                    int G, hipStream_t st, std::vector<BRun> &result, double *seconds)
 {
     Batch b;
     b.st = st;
-    kg_status s = setup(b, runs, nruns, W, L);
+    kg_status s = setup(b, runs, nruns, tune, L);
     if (s != KG_OK) return s;
     if ((s = init(b)) != KG_OK) return s;
     BCHK(hipStreamSynchronize(st));
@@ -534,23 +562,34 @@ kg_status run_batch(const kg_run_desc *runs, int nruns, const std::vector<int> &
     long tasks_live = 0;
     for (const Class &c : b.cls) tasks_live += (long)c.nlist;
     long done = 0;
+    // Replays stay queued one ahead: after launching replay k the host waits
+    // for replay k-1 and reads the active count it (or a later replay) left
+    // in pinned memory, so the GPU never idles on the host.  A replay that
+    // runs after every run has retired does nothing (retired runs' tasks are
+    // skipped on the device).
+    long k = 0;
     while (active > 0 && done < max_steps) {
         const int left = max_steps - (int)done;
         if (left >= G) {
             BCHK(hipGraphLaunch(b.gexec, st));
+            BCHK(hipEventRecord(b.done_ev[k & 1], st));
             done += G;
+            if (k > 0) {
+                BCHK(hipEventSynchronize(b.done_ev[(k - 1) & 1]));
+                active = *(volatile int *)b.h_active;
+            }
+            ++k;
         } else {
             for (const Class &c : b.cls) enqueue_steps(b, c, st, left);
             BCHK(hipGetLastError());
             done += left;
+            BCHK(hipStreamSynchronize(st));
+            k = 0;
         }
-        BCHK(hipMemcpyAsync(b.host.data(), b.d_runs, sizeof(BRun) * nruns, hipMemcpyDeviceToHost, st));
-        BCHK(hipStreamSynchronize(st));
-        int a = 0;
-        for (int r = 0; r < nruns; ++r) a += b.host[r].flag == 0;
-        active = a;
         // drop retired runs from the task lists once enough of them are gone
-        if (active > 0 && active < 0.8 * tasks_live) {
+        if (active > 0 && active < 0.8 * tasks_live && done < max_steps) {
+            BCHK(hipStreamSynchronize(st));
+            k = 0;
             if ((s = compact(b, 0, active)) != KG_OK) return s;
             tasks_live = active;
             (void)hipGraphExecDestroy(b.gexec);
@@ -588,25 +627,49 @@ kg_status run_batch(const kg_run_desc *runs, int nruns, const std::vector<int> &
     return KG_OK;
 }
 
-// Tile width per size: measured on a small batch of stable runs of that size.
-int tune_width(int n, double L, hipStream_t st, double dt)
+// Launch parameters for the sizes in `todo`, measured on the batch itself:
+// the sizes share the GPU as concurrent graph branches, so a size's best
+// parameters depend on the others'.  A trial steps a sample of the batch's
+// runs (every k-th, at most 128, at most 60 steps each); coordinate descent
+// over the sizes (largest first) and, per size, tile width, workgroups per
+// CU and chunk size, keeping the fastest setting found so far.
+std::map<int, Tune> tune_mix(const kg_run_desc *runs, int nruns, std::map<int, Tune> tune,
+                             const std::vector<int> &todo, double L, hipStream_t st)
 {
-    const int R = 16, steps = 20;
-    std::vector<kg_run_desc> d(R);
-    for (int i = 0; i < R; ++i) d[i] = kg_run_desc{n, 0.5, 1.0, 1.1, 0.9, dt, steps, 0.0};
-    int best = 8;
+    const int step = std::max(1, nruns / 128);
+    std::vector<kg_run_desc> d;
+    for (int r = 0; r < nruns && (int)d.size() < 128; r += step) {
+        d.push_back(runs[r]);
+        d.back().max_steps = std::min(d.back().max_steps, 60);
+    }
     double tbest = 1e30;
-    for (int w : {4, 8}) {
-        std::vector<int> W(R, w);
+    auto trial = [&](const std::map<int, Tune> &m) {
         std::vector<BRun> res;
         double secs = 0;
-        if (run_batch(d.data(), R, W, L, 10, st, res, &secs) != KG_OK) continue;
+        if (run_batch(d.data(), (int)d.size(), m, L, 10, st, res, &secs) != KG_OK) return false;
         if (secs < tbest) {
             tbest = secs;
-            best = w;
+            return true;
         }
+        return false;
+    };
+    trial(tune);
+    std::vector<int> order = todo;
+    std::sort(order.begin(), order.end(), [](int a, int b) { return a > b; });
+    for (int n : order) {
+        auto attempt = [&](Tune t) {
+            std::map<int, Tune> m = tune;
+            m[n] = t;
+            if (trial(m)) tune = m;
+        };
+        for (int w : {4, 8})
+            if (w != tune[n].W) attempt(Tune{w, tune[n].wpc, tune[n].chunk_mb});
+        for (int wpc : {2, 3, 4})
+            if (wpc != tune[n].wpc) attempt(Tune{tune[n].W, wpc, tune[n].chunk_mb});
+        for (double mb : {200.0, 400.0, 800.0})
+            if (mb != tune[n].chunk_mb) attempt(Tune{tune[n].W, tune[n].wpc, mb});
     }
-    return best;
+    return tune;
 }
 
 }  // namespace
@@ -631,33 +694,41 @@ kg_status kg_batch_run(const kg_run_desc *runs, int nruns, kg_run_result *out,
     const int G = opts && opts->graph_steps > 0 ? opts->graph_steps : 10;
     hipStream_t st = (hipStream_t)hip_stream;
 
-    // tile width per size: cache, autotuner, default 8
+    // launch parameters per size: cache, autotuner, defaults
     std::string cpath;
     if (opts && opts->tune_cache) cpath = opts->tune_cache;
     else if (const char *e = std::getenv("KG_TUNE_CACHE")) cpath = e;
     auto cache = load_cache(cpath);
-    std::map<int, int> width;
-    bool changed = false;
+    std::map<int, Tune> tune;
+    std::vector<int> todo;  // sizes without cached parameters
     for (int r = 0; r < nruns; ++r) {
         const int n = runs[r].n;
-        if (width.count(n)) continue;
-        auto it = cache.find(cache_key(n));
-        if (it != cache.end() && (it->second == 4 || it->second == 8)) {
-            width[n] = it->second;
-        } else if (opts && opts->tune) {
-            width[n] = tune_width(n, L, st, runs[r].dt);
-            cache[cache_key(n)] = width[n];
-            changed = true;
+        if (tune.count(n)) continue;
+        auto w = cache.find(cache_key(n, "W")), p = cache.find(cache_key(n, "wpc")),
+             c = cache.find(cache_key(n, "chunk_mb"));
+        tune[n] = Tune{};
+        if (w != cache.end() && p != cache.end() && c != cache.end() &&
+            (w->second == 4 || w->second == 8) && p->second >= 1 && p->second <= 4 &&
+            c->second >= 0) {
+            tune[n].W = w->second;
+            tune[n].wpc = p->second;
+            tune[n].chunk_mb = c->second;
         } else {
-            width[n] = 8;
+            todo.push_back(n);
         }
     }
-    if (changed) save_cache(cpath, cache);
-    std::vector<int> W(nruns);
-    for (int r = 0; r < nruns; ++r) W[r] = width[runs[r].n];
+    if (opts && opts->tune && !todo.empty()) {
+        tune = tune_mix(runs, nruns, tune, todo, L, st);
+        for (int n : todo) {
+            cache[cache_key(n, "W")] = tune[n].W;
+            cache[cache_key(n, "wpc")] = tune[n].wpc;
+            cache[cache_key(n, "chunk_mb")] = (int)tune[n].chunk_mb;
+        }
+        save_cache(cpath, cache);
+    }
 
     std::vector<BRun> res;
-    kg_status s = run_batch(runs, nruns, W, L, G, st, res, opts ? opts->seconds : nullptr);
+    kg_status s = run_batch(runs, nruns, tune, L, G, st, res, opts ? opts->seconds : nullptr);
     if (s != KG_OK) return s;
     for (int r = 0; r < nruns; ++r) {
         const BRun &R = res[r];

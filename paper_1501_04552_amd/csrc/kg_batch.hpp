@@ -230,4 +230,20 @@ __global__ __launch_bounds__(256) void kb_finalize(BRun *runs, const int *list, 
     }
 }
 
+// Number of active runs (flag 0) into *active: one workgroup, read back by
+// the host after each graph replay instead of the whole run table.
+__global__ __launch_bounds__(256) void kb_count_active(const BRun *runs, int nruns, int *active)
+{
+    __shared__ int red[256];
+    int c = 0;
+    for (int r = threadIdx.x; r < nruns; r += 256) c += runs[r].flag == 0;
+    red[threadIdx.x] = c;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *active = red[0];
+}
+
 }  // namespace kg

@@ -130,14 +130,29 @@ def test_batch_large_sizes_match_oracle(kg):
 
 
 def test_batch_sweep_sizes_and_autotuner(kg, tmp_path):
-    """The sweep's grid sizes, with the tile-width autotuner writing its cache."""
+    """The sweep's grid sizes, with the autotuner writing its cache: per size
+    the tile width, the persistent workgroups per CU and the chunk size.  The
+    tuned launches give the defaults' results: bitwise for the blow-up
+    levels and max|u| (workgroups and chunks only change who computes a
+    column, and a maximum has no order), energies to 1e-13 (a different tile
+    width regroups the per-workgroup energy partials)."""
     runs = [dict(n=n, A=A, sigma=(1.0, 0.8, 1.2), dt=0.005, max_steps=40, threshold=1e3)
             for n in ki.SWEEP_SIZES for A in (0.7, 3.0)]
     cache = str(tmp_path / "tune.json")
     res, _ = kg.kg_batch_run(runs, tune=True, tune_cache=cache)
     table = json.load(open(cache))
-    assert set(table) == {f"fp64/{n}" for n in ki.SWEEP_SIZES}
-    assert all(v in (4, 8) for v in table.values())
+    assert set(table) == {f"fp64/{n}/{k}" for n in ki.SWEEP_SIZES for k in ("W", "wpc", "chunk_mb")}
+    for n in ki.SWEEP_SIZES:
+        assert table[f"fp64/{n}/W"] in (4, 8)
+        assert table[f"fp64/{n}/wpc"] in (2, 3, 4)
+        assert table[f"fp64/{n}/chunk_mb"] in (200, 400, 800)
+    ref, _ = kg.kg_batch_run(runs)  # defaults, no cache
+    for a, b in zip(res, ref):
+        for k in ("blew_up", "steps_done", "t_blowup", "max_abs_u"):
+            assert a[k] == b[k], k
+        assert abs(a["E0"] - b["E0"]) <= 1e-13 * abs(b["E0"])
+        assert (np.isnan(a["E_final"]) and np.isnan(b["E_final"])) or \
+            abs(a["E_final"] - b["E_final"]) <= 1e-13 * abs(b["E_final"])
     res2, _ = kg.kg_batch_run(runs, tune=True, tune_cache=cache)  # cached widths reused
     for a, b in zip(res, res2):
         assert a["blew_up"] == b["blew_up"] and a["steps_done"] == b["steps_done"]
