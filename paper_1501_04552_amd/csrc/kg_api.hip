@@ -596,7 +596,7 @@ void enqueue_step(Plan &p, long m, hipStream_t st, F &&mark, hipStream_t side = 
     }
     p.ops->z(p, Z_STEP, Sp, Sc, p.invM, 0);
     mark(K_Z);
-    finalize(p, (int)p.ops->z_blocks(p.ntx), p.p.blowup_threshold, 0);
+    finalize(p, (int)p.ops->z_step_parts(p.ntx), p.p.blowup_threshold, 0);
     mark(K_FIN);
     p.stream = keep;
 }

@@ -88,6 +88,16 @@ __device__ __forceinline__ void block_max_sum(double mx, double sm, double *out)
     }
 }
 
+// x where `on`, else 0, selected per component.  Written as one select of
+// two complex values, the compiler may turn it into a load through a
+// selected address (one of them a local zero), which moves register arrays
+// to scratch memory and global loads to flat ones.
+template <typename T>
+__device__ __forceinline__ cx<T> keep(bool on, cx<T> x)
+{
+    return mk(on ? x.re : (T)0, on ? x.im : (T)0);
+}
+
 // The x and y passes load and store the working field with ordinary
 // (cached) accesses: a step runs its y-inverse / x / y-forward chain slab by
 // slab of z planes so that each slab's intermediate fields stay in the GPU's
@@ -215,7 +225,7 @@ __device__ __forceinline__ void xbody(const XArgs<T> &a, long blk, cx<T> *rows, 
 #pragma unroll
         for (int j = 0; j < E; ++j) {
             const int k = t + j * TPL;
-            cx<T> x1 = act ? l1[j] : mk<T>(0, 0), x2 = act ? l2[j] : mk<T>(0, 0);
+            cx<T> x1 = keep(act, l1[j]), x2 = keep(act, l2[j]);
             if (k == 0 || k == NH) {
                 x1.im = 0;
                 x2.im = 0;
@@ -331,7 +341,7 @@ __device__ __forceinline__ void xbody_c(const XArgs<T> &a, long blk, cx<T> *rows
 #pragma unroll
         for (int j = 0; j < E; ++j) ld[j] = q[t + j * TPL];
 #pragma unroll
-        for (int j = 0; j < E; ++j) v[j] = act ? ld[j] : mk<T>(0, 0);
+        for (int j = 0; j < E; ++j) v[j] = keep(act, ld[j]);
         fft_line<T, N, 1, XSY, C::SH>(v, r, 1, t, a.tw, 1);
         // v[j] = u[m], m = t + j*TPL
         if constexpr (MODE == X_C2R) {
@@ -436,7 +446,7 @@ __device__ __forceinline__ void ybody(const YArgs<T> &a, long blk, cx<T> *lds)
 #pragma unroll
     for (int j = 0; j < E; ++j) {
         const cx<T> x = g[(long)(t + j * TPL) * a.P];
-        v[j] = act ? x : mk<T>(0, 0);
+        v[j] = keep(act, x);
     }
     fft_line<T, N, DIR>(v, lds + c + W * b, W * B, t, a.tw, 1,
                         YPRE ? &pre : nullptr);
@@ -528,6 +538,44 @@ __device__ __forceinline__ void coeffs(int mx, int my, int mz, double ks2, doubl
     be = dt * dt * inv;
 }
 
+// The eq. (2) update of one mode (mx, my, mz) in FP64 from the stored levels
+// vc = v^n and vp (v^{n-1}, or Delta^n in the increment form) and the
+// transformed nonlinear term nl: nv = v^{n+1} and, in the increment form,
+// nd = Delta^{n+1} = Delta^n - (2 - alpha) v^n + beta N^n, both rounded to T
+// once.  Adds wgt times the mode's linear energy of (v^n, v^{n+1}) to esum
+// (wgt = 0: a padding column, nothing added).
+template <typename T>
+__device__ __forceinline__ void zupdate(int mx, int my, int mz, double ks2, double dt, cx<T> vc,
+                                        cx<T> vp, cx<T> nl, double wgt, double idt2, cx<T> &nv,
+                                        cx<T> &nd, double &esum)
+{
+    double al, be, w2;
+    coeffs(mx, my, mz, ks2, dt, al, be, w2);
+    double nr, ni, dr, di;  // v^{n+1} and v^{n+1} - v^n in FP64
+    if constexpr (increment_form<T>()) {
+        const double c2 = 2.0 - al;
+        dr = (double)vp.re - c2 * (double)vc.re + be * (double)nl.re;
+        di = (double)vp.im - c2 * (double)vc.im + be * (double)nl.im;
+        nr = (double)vc.re + dr;
+        ni = (double)vc.im + di;
+    } else {
+        nr = al * (double)vc.re - (double)vp.re + be * (double)nl.re;
+        ni = al * (double)vc.im - (double)vp.im + be * (double)nl.im;
+        dr = nr - (double)vc.re;
+        di = ni - (double)vc.im;
+    }
+    nv = mk((T)nr, (T)ni);
+    nd = mk((T)dr, (T)di);
+    if (wgt != 0.0) {
+        const double sr = nr + (double)vc.re, sim = ni + (double)vc.im;
+        esum += wgt * ((dr * dr + di * di) * idt2 + 0.25 * w2 * (sr * sr + sim * sim));
+    }
+    // the sum is formed here, mode by mode: left to the scheduler, the
+    // additions (whose order is fixed) sink past the inverse transform and
+    // keep every mode's term live in the meantime
+    asm volatile("" : "+v"(esum));
+}
+
 // One workgroup's tile of the z pass: columns tile*W.. of B consecutive ky.
 template <typename T, int N, int W, int MODE>
 __device__ __forceinline__ void zbody(const ZArgs<T> &a, long blk, cx<T> *lds, double *part)
@@ -584,7 +632,7 @@ __device__ __forceinline__ void zbody(const ZArgs<T> &a, long blk, cx<T> *lds, d
             // (conditional loads here measured faster than unconditional
             // ones in FP32, and equal in FP64)
 #pragma unroll
-            for (int j = 0; j < E; ++j) v[j] = act ? ld_nt(g + (t + j * TPL) * zs) : zero;
+            for (int j = 0; j < E; ++j) v[j] = keep(act, ld_nt(g + (t + j * TPL) * zs));
             fft_line<T, N, -1>(v, lline, W * B, t, a.tw, 1);
         } else {
 #pragma unroll
@@ -618,7 +666,7 @@ __device__ __forceinline__ void zbody(const ZArgs<T> &a, long blk, cx<T> *lds, d
                 coeffs(mxx, my, mz, a.ks2, a.dt, al, be, w2);
                 const long si = sbase + (long)kz * W;
                 const cx<T> vc = a.Sc[si];
-                const cx<T> nl = a.chi != 0.0 && keep_xy && abs(mz) <= kcut ? a.Sp[si] : zero;
+                const cx<T> nl = keep(a.chi != 0.0 && keep_xy && abs(mz) <= kcut, a.Sp[si]);
                 double re, im;
                 if constexpr (increment_form<T>()) {
                     // Delta^0 = v^0 - v^{-1} = (2a/(1+a)) v^0 + dt F[u_t0] - (beta/2) chi N^0
@@ -663,38 +711,20 @@ __device__ __forceinline__ void zbody(const ZArgs<T> &a, long blk, cx<T> *lds, d
           for (int i = 0; i < ZB; ++i) {
             const int j = h * ZB + i;
             const int kz = t + j * TPL, mz = kz <= N / 2 ? kz : kz - N;
-            double al, be, w2;
-            coeffs(mxx, my, mz, a.ks2, a.dt, al, be, w2);
             const long si = sbase + (long)kz * W;
-            const cx<T> vc = vcs[i], vp = vps[i];
-            const cx<T> nl = keep_xy && abs(mz) <= kcut ? v[j] : zero;
-            double nr, ni, dr, di;  // v^{n+1} and v^{n+1} - v^n in FP64
-            if constexpr (increment_form<T>()) {
-                // Delta^{n+1} = Delta^n - (2 - alpha) v^n + beta N^n
-                const double c2 = 2.0 - al;
-                dr = (double)vp.re - c2 * (double)vc.re + be * (double)nl.re;
-                di = (double)vp.im - c2 * (double)vc.im + be * (double)nl.im;
-                nr = (double)vc.re + dr;
-                ni = (double)vc.im + di;
-            } else {
-                nr = al * (double)vc.re - (double)vp.re + be * (double)nl.re;
-                ni = al * (double)vc.im - (double)vp.im + be * (double)nl.im;
-                dr = nr - (double)vc.re;
-                di = ni - (double)vc.im;
-            }
-            const cx<T> nv = mk((T)nr, (T)ni);
+            const cx<T> nl = keep(keep_xy && abs(mz) <= kcut, v[j]);
+            cx<T> nv, nd;
+            zupdate(mxx, my, mz, a.ks2, a.dt, vcs[i], vps[i], nl, act ? wgt : 0.0, idt2, nv, nd, esum);
             if (act) {
                 if constexpr (increment_form<T>()) {
                     st_nt(a.Sc + si, nv);
-                    st_nt(a.Sp + si, mk((T)dr, (T)di));
+                    st_nt(a.Sp + si, nd);
                 } else {
                     st_nt(a.Sp + si, nv);
                 }
-                const double sr = nr + (double)vc.re, sim = ni + (double)vc.im;
-                esum += wgt * ((dr * dr + di * di) * idt2 + 0.25 * w2 * (sr * sr + sim * sim));
             }
             // the stored level, scaled as a resumed run scales it (Z_INV_STATE)
-            v[j] = act ? scale(nv, (T)a.scale) : zero;
+            v[j] = keep(act, scale(nv, (T)a.scale));
           }
         }
         __syncthreads();
@@ -707,23 +737,27 @@ __device__ __forceinline__ void zbody(const ZArgs<T> &a, long blk, cx<T> *lds, d
                 v[j] = mk((T)(((double)x.re - (double)y.re) * a.scale),
                           (T)(((double)x.im - (double)y.im) * a.scale));
             } else {
-                v[j] = act ? scale(a.Sc[si], (T)a.scale) : zero;
+                v[j] = keep(act, scale(a.Sc[si], (T)a.scale));
             }
         }
     } else if constexpr (MODE == Z_INV_Q) {
 #pragma unroll
-        for (int j = 0; j < E; ++j) v[j] = act ? scale(g[(t + j * TPL) * zs], (T)a.scale) : zero;
+        for (int j = 0; j < E; ++j) v[j] = keep(act, scale(g[(t + j * TPL) * zs], (T)a.scale));
         __syncthreads();
     }
     // Recompute the inverse transform's LDS addresses and the store addresses
     // here rather than keep those of the forward transform and the loads live
-    // (an empty asm hides the earlier values of t and g from the compiler).
+    // (an empty asm hides the earlier values of t and of g's offset from the
+    // compiler; g itself stays a global pointer, so the stores stay global
+    // rather than flat ones).
     int ti = t;
-    asm volatile("" : "+v"(ti), "+v"(g));
+    long go = g - a.Q;
+    asm volatile("" : "+v"(ti), "+v"(go));
+    cx<T> *gi = a.Q + go;
     fft_line<T, N, 1>(v, lline, W * B, ti, a.tw, 1);
     if (act) {
 #pragma unroll
-        for (int j = 0; j < E; ++j) st_nt(g + (ti + j * TPL) * zs, v[j]);
+        for (int j = 0; j < E; ++j) st_nt(gi + (ti + j * TPL) * zs, v[j]);
     }
     if constexpr (MODE == Z_STEP) block_max_sum<NT>(0.0, esum, part);
 }
@@ -754,6 +788,129 @@ void k_zpass(ZArgs<T> a)
         if (a.ctl->flag) return;
     }
     zbody<T, N, W, MODE>(a, blockIdx.x, lds, a.part + 2 * blockIdx.x);
+}
+
+// The z pass of a step (Z_STEP) as a persistent, software-pipelined kernel:
+// workgroup g takes the tiles g, g + G, g + 2G, ... (G = gridDim.x, about
+// one workgroup per CU) and keeps the next tile's loads in flight while it
+// transforms the current one:
+//   top:     PF = 1: the current tile's Q values arrive (issued one tile
+//            earlier) and the next tile's Q loads are issued; PF = 0: the
+//            current tile's Q loads are issued and arrive;
+//   forward z transform; the state loads (issued one tile earlier) arrive;
+//   update, energy term, state stores; the next tile's state loads issued;
+//   inverse z transform; Q stores.
+// Loads complete in issue order (one counter per wave), so every wait above
+// leaves the loads issued after it in flight; the twiddle table is copied to
+// LDS first so that no table load is queued behind the prefetches.  Each
+// workgroup sums its energy terms in its fixed tile order and writes one
+// partial, G partials in all.  The values stored are those of k_zpass's
+// Z_STEP (same transforms, same update).
+template <typename T, int N, int W, int PF>
+__global__ __launch_bounds__((YZCfg<N, W>::NT)) void k_zstep(ZArgs<T> a, int nblk)
+{
+    using C = YZCfg<N, W>;
+    constexpr int E = Radix<N>::E, TPL = C::TPL, B = C::B, NT = C::NT;
+    __shared__ cx<T> lds[W * B * lslots<N>()];
+    __shared__ cx<T> twl[N];
+    if (a.ctl->flag) return;
+    for (int i = threadIdx.x; i < N; i += NT) twl[i] = a.tw[i];
+    const double idt2 = 1.0 / (a.dt * a.dt);
+    const int kcut = keep_cut<N>(a.dkc);
+    double esum = 0.0;
+    // This thread's place in a tile, (column c, position t, row b), read
+    // through an empty asm wherever addresses are formed: the compiler then
+    // rebuilds them in each tile instead of hoisting every loop-invariant
+    // offset (some hundred registers) out of the tile loop.
+    struct Lane {
+        int c, t, b;
+    };
+    auto lane = []() {
+        Lane l{(int)threadIdx.x % W, ((int)threadIdx.x / W) % TPL, (int)threadIdx.x / (W * TPL)};
+        asm volatile("" : "+v"(l.c), "+v"(l.t), "+v"(l.b));
+        return l;
+    };
+    // Q and state addresses of tile blk; rows past the last ky (ragged
+    // workgroups of small grids) are clamped, so every load is
+    // unconditional and in bounds (padding columns are allocated)
+    auto qptr = [&](int blk, const Lane &l) -> cx<T> * {
+        const int ky = (blk / a.ntx) * B + l.b;
+        return a.Q + (long)(ky < N ? ky : 0) * a.P + (blk % a.ntx) * W + l.c + (long)l.t * a.PZ;
+    };
+    auto sptr = [&](cx<T> *S, int blk, const Lane &l) -> cx<T> * {
+        const int ky = (blk / a.ntx) * B + l.b;
+        return S + (((long)(ky < N ? ky : 0) * a.ntx + blk % a.ntx) * N + l.t) * W + l.c;
+    };
+    auto load_q = [&](cx<T> (&q)[E], int blk) {
+        const Lane l = lane();
+        const cx<T> *g = qptr(blk, l);
+#pragma unroll
+        for (int j = 0; j < E; ++j) q[j] = ld_nt(g + (long)j * TPL * a.PZ);
+    };
+    auto load_s = [&](cx<T> (&sc)[E], cx<T> (&sp)[E], int blk) {
+        const Lane l = lane();
+        const cx<T> *gc = sptr(a.Sc, blk, l), *gp = sptr(a.Sp, blk, l);
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+            sc[j] = ld_nt(gc + j * TPL * W);
+            sp[j] = ld_nt(gp + j * TPL * W);
+        }
+    };
+    cx<T> q[E], sc[E], sp[E];
+    if constexpr (PF == 1) load_q(q, blockIdx.x);
+    load_s(sc, sp, blockIdx.x);
+    __syncthreads();  // twiddles in LDS
+    for (int it = blockIdx.x; it < nblk; it += gridDim.x) {
+        int blk = it;
+        asm volatile("" : "+s"(blk));
+        const int nxt = blk + gridDim.x;
+        cx<T> v[E];
+        if constexpr (PF == 1) {
+#pragma unroll
+            for (int j = 0; j < E; ++j) v[j] = q[j];
+            if (nxt < nblk) load_q(q, nxt);
+        } else {
+            load_q(v, blk);
+        }
+        Lane l = lane();
+        const int ky = (blk / a.ntx) * B + l.b, kx = (blk % a.ntx) * W + l.c;
+        const bool act = kx < a.H && ky < N;
+#pragma unroll
+        for (int j = 0; j < E; ++j) v[j] = keep(act, v[j]);
+        fft_line<T, N, -1>(v, lds + l.c + W * l.b, W * B, l.t, twl, 1);
+        l = lane();
+        const int my = ky <= N / 2 ? ky : ky - N, mxx = mode_of<N>(kx);
+        const bool keep_xy = abs(mxx) <= kcut && abs(my) <= kcut;
+        const double wgt = act ? kx_weight<N>(kx, a.cf) : 0.0;
+        cx<T> *gc = sptr(a.Sc, blk, l), *gp = sptr(a.Sp, blk, l);
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+            const int kz = l.t + j * TPL, mz = kz <= N / 2 ? kz : kz - N;
+            const cx<T> nl = keep(keep_xy && abs(mz) <= kcut, v[j]);
+            cx<T> nv, nd;
+            zupdate(mxx, my, mz, a.ks2, a.dt, sc[j], sp[j], nl, wgt, idt2, nv, nd, esum);
+            if (act) {
+                if constexpr (increment_form<T>()) {
+                    st_nt(gc + j * TPL * W, nv);
+                    st_nt(gp + j * TPL * W, nd);
+                } else {
+                    st_nt(gp + j * TPL * W, nv);
+                }
+            }
+            v[j] = keep(act, scale(nv, (T)a.scale));
+        }
+        if (nxt < nblk) load_s(sc, sp, nxt);
+        __syncthreads();
+        l = lane();
+        fft_line<T, N, 1>(v, lds + l.c + W * l.b, W * B, l.t, twl, 1);
+        if (act) {
+            cx<T> *g = qptr(blk, l);
+#pragma unroll
+            for (int j = 0; j < E; ++j) st_nt(g + (long)j * TPL * a.PZ, v[j]);
+        }
+        __syncthreads();  // the next tile's forward transform reuses the LDS
+    }
+    block_max_sum<NT>(0.0, esum, a.part + 2 * blockIdx.x);
 }
 
 // Linear energy partials of a pair of levels stored in the state layout:
