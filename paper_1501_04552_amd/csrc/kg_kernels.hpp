@@ -164,6 +164,7 @@ __device__ __forceinline__ void xbody(const XArgs<T> &a, long blk, cx<T> *rows, 
     constexpr int E = Radix<N>::E, TPL = C::TPL, PPB = C::PPB, RS = C::RS, NH = N / 2;
     // a pair's threads never span two waves, so its stages sync per wave
     constexpr int XSY = (64 % TPL == 0) ? SYNC_WAVE : SYNC_BLOCK;
+    static_assert(E % 2 == 0 && E * TPL == N, "the half-spectrum cases are split by position");
     const int t = threadIdx.x % TPL, l = threadIdx.x / TPL;
     const long pr = blk * PPB + l;
     const bool act = pr < (long)N * N / 2;
@@ -215,23 +216,25 @@ __device__ __forceinline__ void xbody(const XArgs<T> &a, long blk, cx<T> *rows, 
         const long prc = act ? pr : 0;
         const cx<T> *q1 = a.Q + (2 * prc / N) * a.PZ + (2 * prc % N) * a.P, *q2 = q1 + a.P;
         cx<T> l1[E], l2[E];
+        // k = t + j*TPL lies below N/2 for j < E/2 and above it for j > E/2;
+        // for j = E/2 it is N/2 + t (N/2 itself only on thread 0, where both
+        // forms below agree once the imaginary parts are dropped)
 #pragma unroll
         for (int j = 0; j < E; ++j) {
             const int k = t + j * TPL;
-            const int m = k <= NH ? k : N - k;
+            const int m = j < E / 2 ? k : N - k;
             l1[j] = q1[m];
             l2[j] = q2[m];
         }
 #pragma unroll
         for (int j = 0; j < E; ++j) {
-            const int k = t + j * TPL;
-            cx<T> x1 = keep(act, l1[j]), x2 = keep(act, l2[j]);
-            if (k == 0 || k == NH) {
+            cx<T> x1 = l1[j], x2 = l2[j];
+            if ((j == 0 || j == E / 2) && t == 0) {  // k = 0, k = N/2
                 x1.im = 0;
                 x2.im = 0;
             }
             // Z = X1 + i X2 (k <= N/2), conj(X1) + i conj(X2) (k > N/2)
-            v[j] = k <= NH ? mk(x1.re - x2.im, x1.im + x2.re) : mk(x1.re + x2.im, x2.re - x1.im);
+            v[j] = j < E / 2 ? mk(x1.re - x2.im, x1.im + x2.re) : mk(x1.re + x2.im, x2.re - x1.im);
         }
         fft_line<T, N, 1, XSY, C::SH>(v, r, 1, t, a.tw, 1);
         // v[j] = u1[m] + i u2[m], m = t + j*TPL
@@ -266,7 +269,7 @@ __device__ __forceinline__ void xbody(const XArgs<T> &a, long blk, cx<T> *rows, 
 #pragma unroll
         for (int j = 0; j < E; ++j) {
             const T u1 = v[j].re, u2 = v[j].im;
-            v[j] = mk(a.chi * u1 * u1 * u1, a.chi * u2 * u2 * u2);
+            v[j] = mk(a.chi * (u1 * u1 * u1), a.chi * (u2 * u2 * u2));
         }
         stage_sync<XSY>();
     }
@@ -274,19 +277,19 @@ __device__ __forceinline__ void xbody(const XArgs<T> &a, long blk, cx<T> *rows, 
     // positions >= N/2 are the partners N-k of the outputs k = 1..N/2
     stage_sync<XSY>();
 #pragma unroll
-    for (int j = 0; j < E; ++j) {
+    for (int j = E / 2; j < E; ++j) {  // k >= N/2
         const int k = t + j * TPL;
-        if (k >= NH) r[lslot<N, C::SH>(k)] = v[j];
+        r[lslot<N, C::SH>(k)] = v[j];
     }
     stage_sync<XSY>();
     if (act) {
         cx<T> *q1 = a.Q + (2 * pr / N) * a.PZ + (2 * pr % N) * a.P, *q2 = q1 + a.P;
 #pragma unroll
-        for (int j = 0; j < E; ++j) {
+        for (int j = 0; j <= E / 2; ++j) {  // k <= N/2: j < E/2, and k = N/2 on thread 0
             const int k = t + j * TPL;
-            if (k <= NH) {
+            if (j < E / 2 || t == 0) {
                 const cx<T> zk = v[j];
-                const cx<T> zm = k == 0 ? conjg(zk) : conjg(r[lslot<N, C::SH>(N - k)]);
+                const cx<T> zm = (j == 0 && t == 0) ? conjg(zk) : conjg(r[lslot<N, C::SH>(N - k)]);
                 q1[k] = scale(zk + zm, (T)0.5);
                 q2[k] = scale(rot90<-1>(zk - zm), (T)0.5);
             }
@@ -341,7 +344,7 @@ __device__ __forceinline__ void xbody_c(const XArgs<T> &a, long blk, cx<T> *rows
 #pragma unroll
         for (int j = 0; j < E; ++j) ld[j] = q[t + j * TPL];
 #pragma unroll
-        for (int j = 0; j < E; ++j) v[j] = keep(act, ld[j]);
+        for (int j = 0; j < E; ++j) v[j] = ld[j];
         fft_line<T, N, 1, XSY, C::SH>(v, r, 1, t, a.tw, 1);
         // v[j] = u[m], m = t + j*TPL
         if constexpr (MODE == X_C2R) {
@@ -446,7 +449,7 @@ __device__ __forceinline__ void ybody(const YArgs<T> &a, long blk, cx<T> *lds)
 #pragma unroll
     for (int j = 0; j < E; ++j) {
         const cx<T> x = g[(long)(t + j * TPL) * a.P];
-        v[j] = keep(act, x);
+        v[j] = x;
     }
     fft_line<T, N, DIR>(v, lds + c + W * b, W * B, t, a.tw, 1,
                         YPRE ? &pre : nullptr);
@@ -632,7 +635,7 @@ __device__ __forceinline__ void zbody(const ZArgs<T> &a, long blk, cx<T> *lds, d
             // (conditional loads here measured faster than unconditional
             // ones in FP32, and equal in FP64)
 #pragma unroll
-            for (int j = 0; j < E; ++j) v[j] = keep(act, ld_nt(g + (t + j * TPL) * zs));
+            for (int j = 0; j < E; ++j) v[j] = ld_nt(g + (t + j * TPL) * zs);
             fft_line<T, N, -1>(v, lline, W * B, t, a.tw, 1);
         } else {
 #pragma unroll
@@ -724,7 +727,7 @@ __device__ __forceinline__ void zbody(const ZArgs<T> &a, long blk, cx<T> *lds, d
                 }
             }
             // the stored level, scaled as a resumed run scales it (Z_INV_STATE)
-            v[j] = keep(act, scale(nv, (T)a.scale));
+            v[j] = scale(nv, (T)a.scale);
           }
         }
         __syncthreads();
@@ -737,12 +740,12 @@ __device__ __forceinline__ void zbody(const ZArgs<T> &a, long blk, cx<T> *lds, d
                 v[j] = mk((T)(((double)x.re - (double)y.re) * a.scale),
                           (T)(((double)x.im - (double)y.im) * a.scale));
             } else {
-                v[j] = keep(act, scale(a.Sc[si], (T)a.scale));
+                v[j] = scale(a.Sc[si], (T)a.scale);
             }
         }
     } else if constexpr (MODE == Z_INV_Q) {
 #pragma unroll
-        for (int j = 0; j < E; ++j) v[j] = keep(act, scale(g[(t + j * TPL) * zs], (T)a.scale));
+        for (int j = 0; j < E; ++j) v[j] = scale(g[(t + j * TPL) * zs], (T)a.scale);
         __syncthreads();
     }
     // Recompute the inverse transform's LDS addresses and the store addresses
@@ -875,8 +878,6 @@ __global__ __launch_bounds__((YZCfg<N, W>::NT)) void k_zstep(ZArgs<T> a, int nbl
         Lane l = lane();
         const int ky = (blk / a.ntx) * B + l.b, kx = (blk % a.ntx) * W + l.c;
         const bool act = kx < a.H && ky < N;
-#pragma unroll
-        for (int j = 0; j < E; ++j) v[j] = keep(act, v[j]);
         fft_line<T, N, -1>(v, lds + l.c + W * l.b, W * B, l.t, twl, 1);
         l = lane();
         const int my = ky <= N / 2 ? ky : ky - N, mxx = mode_of<N>(kx);
@@ -897,7 +898,7 @@ __global__ __launch_bounds__((YZCfg<N, W>::NT)) void k_zstep(ZArgs<T> a, int nbl
                     st_nt(gp + j * TPL * W, nv);
                 }
             }
-            v[j] = keep(act, scale(nv, (T)a.scale));
+            v[j] = scale(nv, (T)a.scale);
         }
         if (nxt < nblk) load_s(sc, sp, nxt);
         __syncthreads();

@@ -428,3 +428,31 @@ def test_plane_padding_does_not_change_results(kg, monkeypatch, precision, compl
     for u, E in out[1:]:
         assert np.array_equal(u, out[0][0])
         assert E == out[0][1]
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("n", [48, 512])
+def test_persistent_z_pass_matches_tile_kernel(kg, monkeypatch, precision, n):
+    """The step's z pass runs as a persistent workgroup-per-CU kernel
+    (k_zstep) or, with KG_Z_PERSISTENT=0, one workgroup per tile (k_zpass).
+    Both run the same transforms and the same per-mode update, so the levels
+    and fields agree bitwise; only the energy's partial sums are grouped
+    differently (per workgroup), so energies agree to rounding (1e-14
+    relative).  48^3 (radix-3 z lines, ragged tiles) and the benchmark's
+    512^3."""
+    dt = 0.005
+    u0 = ki.gaussian(n, 1.5 if n == 48 else 0.1)
+    out = {}
+    for persistent in ("1", "0"):
+        monkeypatch.setenv("KG_Z_PERSISTENT", persistent)
+        with kg.Solver(n, dt, precision=precision) as s:
+            s.set_state(u0)
+            st, done = s.step(10)
+            assert st == kg.KG_OK and done == 10
+            elin, q4, maxu = s.records(0, 10)
+            out[persistent] = (s.spectrum(0), s.spectrum(1), elin, q4, maxu, s.energy()[0])
+    a, b = out["1"], out["0"]
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    assert np.array_equal(a[3], b[3]) and np.array_equal(a[4], b[4])
+    assert np.allclose(a[2], b[2], rtol=1e-14, atol=0)
+    assert abs(a[5] - b[5]) <= 1e-14 * abs(b[5])
