@@ -229,6 +229,25 @@ def golden_compare(kg, ki, np, torch, n, A, steps=200):
     return out
 
 
+def energy_vs_oracle(np, n, A, dt, series):
+    """The timed run's energy series E^{m-1/2} (every --energy-every levels)
+    against the oracle's run of the same workload (tests/golden/field_<n>_A<A>.npz,
+    written from oracle/ only), at the levels both have."""
+    path = os.path.join(ROOT, "tests", "golden", f"field_{n}_A{A:g}.npz")
+    if not os.path.exists(path):
+        return None
+    g = np.load(path)
+    if abs(float(g["dt"]) - dt) > 1e-15 or np.any(np.asarray(g["sigma"]) != 1.0):
+        return None
+    ref = g["energy"]
+    pts = [(m, e) for m, e in series if m < len(ref)]
+    if not pts:
+        return None
+    rel = [abs(e - ref[m]) / abs(ref[m]) for m, e in pts]
+    return {"levels": [m for m, _ in pts], "max_rel_diff": float(max(rel)),
+            "oracle_levels": int(len(ref) - 1)}
+
+
 def surrogate_leg(mode):
     """The blow-up surrogate on the sweep distribution at 64^3: solver labels,
     training by the library's kernels, held-out accuracy with solver fallback,
@@ -348,6 +367,7 @@ def main():
     cplx = complex_legs() if args.complex == "on" else None
     for m, e in r64["series"]:
         print(f"step {m:5d}  E^(m-1/2) = {e:.15e}", file=sys.stderr)
+    energy_check = energy_vs_oracle(np, n, args.amplitude, dt, r64["series"])
     elapsed, drift, ms = r64["elapsed"], r64["drift"], r64["ms"]
     zi = kg.KERNELS.index("z_update")
     zbytes = r64["kbytes"][zi]
@@ -416,6 +436,7 @@ def main():
         "kernels_ms_sum": float(sum(ms)),
         "copy_GBs": copy_gbs,
         "energy_drift": drift,
+        "energy_vs_oracle": energy_check,
         "fp32": fp32,
         "precision_study": precision_study,
     }

@@ -632,8 +632,8 @@ __device__ __forceinline__ void zbody(const ZArgs<T> &a, long blk, cx<T> *lds, d
     }
     if constexpr (MODE == Z_STEP || MODE == Z_FWD_STATE || MODE == Z_FWD_Q || MODE == Z_START) {
         if (MODE != Z_START || a.has_vel) {
-            // (conditional loads here measured faster than unconditional
-            // ones in FP32, and equal in FP64)
+            // padding columns (kx >= H, allocated) are loaded and transformed
+            // like the others; nothing they produce is stored or summed
 #pragma unroll
             for (int j = 0; j < E; ++j) v[j] = ld_nt(g + (t + j * TPL) * zs);
             fft_line<T, N, -1>(v, lline, W * B, t, a.tw, 1);

@@ -6,14 +6,15 @@ of the second-order scheme of Sec. 1.1.2, eq. (2), for the real cubic
 Klein-Gordon equation (Sec. 1, eq. (1)) on the box [-4 pi, 4 pi)^3 from the
 Gaussian u(0) = A exp(-(x^2/sx^2 + y^2/sy^2 + z^2/sz^2)), u_t(0) = 0.
 
-Field cases (``field_<n>_A<A>.npz``), per stored level m (100, and 200 where
-listed): the physical field u^m on a strided 32^3 subsample
+Field cases (``field_<n>_A<A>.npz``), per stored level m (100, and 200 or
+500 where listed): the physical field u^m on a strided 32^3 subsample
 ``u[::n/32, ::n/32, ::n/32]`` and on the central 16^3 block
 ``u[n/2-8:n/2+8]`` (all three axes), and the L2 norm of the whole field;
 per level 0..last: the energy E^{m-1/2} of Sec. 1.1 (index m), max|u^m| and
-Q4^m = h^3 sum (u^m)^4.  A 200-level case is run as 100 steps and then 100
-more from the two-level restart (u^99, u^100), which reproduces a straight
-run to rounding (~1e-15 relative).
+Q4^m = h^3 sum (u^m)^4.  Runs longer than 100 steps go in segments of 100
+steps, each started from the two-level restart (u^{m-1}, u^m) of the one
+before, which reproduces a straight run to rounding (~1e-15 relative) and
+bounds the memory a segment's output holds.
 
 Sweep cases (``batch_cases.json``): runs of the batched sweep's sizes (96^3,
 128^3) with the blow-up test max|u| > 1e3; per run the blow-up level (-1 if
@@ -48,7 +49,7 @@ FIELD_CASES = [
     (256, 1.5, (1.0, 1.0, 1.0), (100, 200)),
     (384, 0.1, (1.0, 1.0, 1.0), (100,)),
     (384, 1.5, (1.0, 1.0, 1.0), (100,)),
-    (512, 0.1, (1.0, 1.0, 1.0), (100,)),
+    (512, 0.1, (1.0, 1.0, 1.0), (100, 500)),
     (512, 1.5, (1.0, 1.0, 1.0), (100, 200)),
 ]
 
@@ -87,18 +88,18 @@ def make_field(n, A, sigma, levels):
     sub, blk, nrm = samples(r["u"])
     out.update(u100_sub=sub, u100_center=blk, u100_norm=nrm)
     print(f"  {n}^3 A={A}: 100 steps in {time.time() - t0:.0f} s", flush=True)
-    if 200 in levels:
-        r2 = oracle.run(r["u"], DT, 100, threshold=THRESHOLD, mode=oracle.INIT_TWO_LEVEL,
-                        aux=r["u_prev"])
-        del r
-        assert r2["blowup_step"] < 0, "reference run blew up"
-        # level 0 of the restart is level 100 of the first run
-        energy += list(r2["energy"][1:])
-        maxu += list(r2["maxu"][1:])
-        q4 += list(r2["q4"][1:])
-        sub, blk, nrm = samples(r2["u"])
-        out.update(u200_sub=sub, u200_center=blk, u200_norm=nrm)
-        print(f"  {n}^3 A={A}: 200 steps in {time.time() - t0:.0f} s", flush=True)
+    for m in range(200, max(levels) + 1, 100):
+        r = oracle.run(r["u"], DT, 100, threshold=THRESHOLD, mode=oracle.INIT_TWO_LEVEL,
+                       aux=r["u_prev"])
+        assert r["blowup_step"] < 0, "reference run blew up"
+        # level 0 of a restart is the last level of the segment before
+        energy += list(r["energy"][1:])
+        maxu += list(r["maxu"][1:])
+        q4 += list(r["q4"][1:])
+        if m in levels:
+            sub, blk, nrm = samples(r["u"])
+            out.update({f"u{m}_sub": sub, f"u{m}_center": blk, f"u{m}_norm": nrm})
+        print(f"  {n}^3 A={A}: {m} steps in {time.time() - t0:.0f} s", flush=True)
     out.update(energy=np.array(energy), maxu=np.array(maxu), q4=np.array(q4),
                oracle_threads=oracle.num_threads())
     path = os.path.join(HERE, field_name(n, A))

@@ -9,9 +9,9 @@ Fields are compared on a strided 32^3 subsample and on the central 16^3 block
 (where the Gaussian sits), plus the whole field's L2 norm; energies (Sec. 1.1,
 E^{m-1/2} at every level), max|u^m| and Q4^m at every level.
 
-Tolerances.  FP64: relative L2 <= 1e-11 after 100 and 200 steps (the target
-for the double-precision path); per-level energies, max|u| and Q4 to 1e-11
-relative.  Both sides round each transform at ~log2(M) eps ~ 3e-15 and these
+Tolerances.  FP64: relative L2 <= 1e-11 at every stored level (100, and 200
+or 500 steps; the target for the double-precision path); per-level energies,
+max|u| and Q4 to 1e-11 relative.  Both sides round each transform at ~log2(M) eps ~ 3e-15 and these
 runs amplify rounding weakly (A = 0.1 is nearly linear; A = 1.5 disperses),
 so the expected difference is ~1e-13.  FP32 (FP32 transforms and cube, FP64
 update and reductions, increment-form levels): relative L2 <= 1e-4 against
@@ -85,15 +85,13 @@ def test_fp64_matches_oracle_at_full_size(kg, n, A):
     dt = float(g["dt"])
     with kg.Solver(n, dt, blowup_threshold=1e3) as s:
         s.set_state(torch.from_numpy(ki.gaussian(n, A, tuple(g["sigma"]))).cuda())
-        st, done = s.step(100)
-        assert st == kg.KG_OK and done == 100
-        compare_level(s, g, n, 100, 1e-11)
-        compare_series(s, g, 100, 1e-11, 1e-11)
-        if 200 in g["levels"]:
-            st, done = s.step(100)
-            assert st == kg.KG_OK and done == 200
-            compare_level(s, g, n, 200, 1e-11)
-            compare_series(s, g, 200, 1e-11, 1e-11)
+        at = 0
+        for m in sorted(int(x) for x in g["levels"]):
+            st, done = s.step(m - at)
+            assert st == kg.KG_OK and done == m - at
+            at = m
+            compare_level(s, g, n, m, 1e-11)
+            compare_series(s, g, m, 1e-11, 1e-11)
 
 
 @pytest.mark.parametrize("n", [256, 512])
