@@ -101,6 +101,14 @@ size_t kg_workspace_bytes(const kg_params *p);
  * work is enqueued on (NULL = default stream).  No kernel runs.
  * Errors: KG_E_INVALID (NULL arguments, dt <= 0), KG_E_UNSUPPORTED_SIZE,
  * KG_E_NOMEM (ws_bytes too small or allocation failure), KG_E_HIP.
+ * Read at plan creation, for experiments (results are bitwise the same for
+ * every setting unless stated): KG_SLAB_MB (z planes per slab of the
+ * y-inverse / x / y-forward chain, in MB; 0: one slab), KG_SLAB_STREAMS (1 or
+ * 2 streams for the slabs), KG_PLANE_PAD (bytes between z planes of the
+ * working field, a multiple of 128), KG_TILE_W (tile width of the y and z
+ * passes: 4 or 8 in FP64, 8 or 16 in FP32; changes the energy's summation
+ * order), KG_Z_PERSISTENT=0 (the step's z pass one workgroup per tile instead
+ * of persistent workgroups; changes the energy's summation order).
  */
 kg_status kg_plan(const kg_params *p, void *d_workspace, size_t ws_bytes, void *hip_stream,
                   kg_plan_t **out);
@@ -252,8 +260,9 @@ typedef struct {
 typedef struct {
     double L;               /* box length per axis; <= 0 selects 8*pi */
     int graph_steps;        /* steps per captured graph; <= 0 selects 10 */
-    int tune;               /* nonzero: tune the tile width of sizes missing from the cache */
-    const char *tune_cache; /* tile-width cache (JSON); NULL: $KG_TUNE_CACHE, else none */
+    int tune;               /* nonzero: tune the launch parameters (tile width, workgroups
+                               per CU, chunk size) of sizes missing from the cache */
+    const char *tune_cache; /* launch-parameter cache (JSON); NULL: $KG_TUNE_CACHE, else none */
     double *seconds;        /* if not NULL: wall time of the stepping (set-up excluded) */
 } kg_batch_opts;
 
