@@ -229,6 +229,30 @@ def golden_compare(kg, ki, np, torch, n, A, steps=200):
     return out
 
 
+def pcie_inclusive(torch, u0, elapsed, steps):
+    """The rate when the initial field comes from host memory and u of the
+    last level goes back to it: the timed steps plus one host-to-device and
+    one device-to-host copy of a real field (pageable numpy memory, as a
+    caller's arrays would be).  A note beside `value`, never `value`."""
+    reps = 3
+    t_h2d = t_d2h = 1e30
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        d = torch.from_numpy(u0).cuda()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        h = d.cpu()
+        t2 = time.perf_counter()
+        t_h2d, t_d2h = min(t_h2d, t1 - t0), min(t_d2h, t2 - t1)
+        del d, h
+    total = elapsed + t_h2d + t_d2h
+    return {"steps_per_s": steps / total, "h2d_seconds": t_h2d, "d2h_seconds": t_d2h,
+            "field_GB": u0.nbytes / 1e9,
+            "note": f"{steps} timed steps plus one {u0.nbytes / 1e9:.2f} GB field each way over "
+                    "PCIe (best of 3 copies each)"}
+
+
 def energy_vs_oracle(np, n, A, dt, series):
     """The timed run's energy series E^{m-1/2} (every --energy-every levels)
     against the oracle's run of the same workload (tests/golden/field_<n>_A<A>.npz,
@@ -368,6 +392,7 @@ def main():
     for m, e in r64["series"]:
         print(f"step {m:5d}  E^(m-1/2) = {e:.15e}", file=sys.stderr)
     energy_check = energy_vs_oracle(np, n, args.amplitude, dt, r64["series"])
+    pcie = pcie_inclusive(torch, u0, r64["elapsed"], args.steps)
     elapsed, drift, ms = r64["elapsed"], r64["drift"], r64["ms"]
     zi = kg.KERNELS.index("z_update")
     zbytes = r64["kbytes"][zi]
@@ -437,6 +462,7 @@ def main():
         "copy_GBs": copy_gbs,
         "energy_drift": drift,
         "energy_vs_oracle": energy_check,
+        "pcie_inclusive": pcie,
         "fp32": fp32,
         "precision_study": precision_study,
     }
