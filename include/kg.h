@@ -51,7 +51,8 @@ typedef enum {
     KG_E_UNSUPPORTED_SIZE = 2, /* n not a supported grid size */
     KG_E_NOMEM = 3,            /* workspace too small or allocation failed */
     KG_E_HIP = 4,              /* HIP runtime error */
-    KG_BLOWUP = 5              /* max|u| exceeded the threshold or became non-finite */
+    KG_BLOWUP = 5,             /* max|u| exceeded the threshold or became non-finite */
+    KG_E_ENERGY = 6            /* the energy alarm stopped the run (kg_set_energy_alarm) */
 } kg_status;
 
 enum { KG_FP64 = 0, KG_FP32 = 1 };
@@ -139,7 +140,8 @@ kg_status kg_set_state(kg_plan_t *plan, const double *u0, const double *aux, int
  * of the level just used is checked; on a blow-up the remaining kernels
  * return at once and the counter stops at the blown level n.  With
  * KG_STEP_SYNC the call synchronises, stores the step counter in
- * *steps_done (may be NULL) and returns KG_BLOWUP if the run has blown up.
+ * *steps_done (may be NULL) and returns KG_BLOWUP if the run has blown up
+ * (KG_E_ENERGY if the energy alarm stopped it, see kg_set_energy_alarm).
  * With KG_STEP_TIMED the kernels are launched one by one instead, every
  * launch bracketed by HIP events on the plan's stream, and the call
  * synchronises; kg_kernel_times then reports the per-kernel averages.
@@ -162,7 +164,8 @@ kg_status kg_kernel_times(const kg_plan_t *plan, double ms[5], int *nsteps);
  * The discrete form is this library's reading of the continuous energy; its
  * linear part is exactly conserved by eq. (2).  Q4^n is reduced on demand
  * (one read-only pass over the field); the stepping path never pays for it.
- * Synchronises the stream.  E or t may be NULL.  KG_BLOWUP after a blow-up.
+ * Synchronises the stream.  E or t may be NULL.  KG_BLOWUP after a blow-up,
+ * KG_E_ENERGY after the energy alarm stopped the run.
  */
 kg_status kg_energy(kg_plan_t *plan, double *E, double *t);
 
@@ -186,13 +189,32 @@ kg_status kg_records(kg_plan_t *plan, int first, int count, double *elin, double
                      double *maxu);
 
 /*
- * Steps done, blow-up flag and blown level (-1 if none), and max_j |u^n_j|
- * of the newest level n (the blown level after a blow-up; NaN if that level
+ * Steps done, stop flag (0 running, 1 blown up, 2 stopped by the energy
+ * alarm) and the level the run stopped at (-1 if none), and max_j |u^n_j|
+ * of the newest level n (the stopping level once stopped; NaN if that level
  * holds a non-finite value).  Any output may be NULL; max_abs_u costs one
- * read-only pass over the field unless the run has blown up.  Synchronises.
+ * read-only pass over the field unless the run has stopped.  Synchronises.
  */
 kg_status kg_stats(kg_plan_t *plan, int *steps_done, int *blown_up, int *blowup_step,
                    double *max_abs_u);
+
+/*
+ * Energy alarm (Sec. 1.1: the conserved energy serves as a check that code,
+ * libraries and hardware computed the run correctly).  With rel_tol > 0,
+ * every step compares the newest energy E^{n-1/2} (the value kg_energies
+ * returns) with the energy E^{-1/2} of the initial pair set by kg_set_state
+ * (after kg_load_state: of the saved run's initial pair); once |E^{n-1/2} - E^{-1/2}| > rel_tol |E^{-1/2}|,
+ * or E^{n-1/2} is not finite, the run stops at level n exactly as on a
+ * blow-up (the remaining kernels return, the counter stays at n, kg_stats
+ * reports flag 2 and level n) and kg_step with KG_STEP_SYNC, kg_energy and
+ * the other synchronising calls return KG_E_ENERGY.  rel_tol = 0 turns the
+ * alarm off (the default).  The setting belongs to the plan: it survives
+ * kg_set_state and kg_load_state and applies to graphs already captured.
+ * The linear energy is conserved to rounding (about 1e-13 relative over
+ * hundreds of steps); the nonlinear one drifts by O(dt^2), so its tolerance
+ * must sit above that drift.  KG_E_INVALID for a negative or non-finite rel_tol.
+ */
+kg_status kg_set_energy_alarm(kg_plan_t *plan, double rel_tol);
 
 /* u^n (n = steps done) in physical space, n^3 doubles (2*n^3 interleaved
  * re, im for a complex field).  Off the hot path.  Same as
@@ -396,6 +418,17 @@ kg_status kg_debug_time_kernel(kg_plan_t *plan, int kernel, int reps, float *ms)
  */
 kg_status kg_debug_copy(void *d_dst, const void *d_src, size_t bytes, int reps, void *hip_stream,
                         float *ms);
+
+/*
+ * Forced fault for tests of the energy alarm: multiplies the stored
+ * coefficient v^n_k of the newest level n, k = (kx, ky, kz) with kx in [0, H)
+ * (H = n/2 + 1, or n for a complex field) and ky, kz in [0, n), by `factor`
+ * and rebuilds the working field from the changed level, so the next step
+ * starts from it.  FP32 plans keep v^{n-1} unchanged.  KG_E_INVALID for an
+ * index out of range, a non-finite factor, or before kg_set_state; after a
+ * stop, the stop's status.  Synchronises.
+ */
+kg_status kg_debug_scale_mode(kg_plan_t *plan, int kx, int ky, int kz, double factor);
 
 /* Algorithmic HBM bytes one launch of a step kernel moves (see kg_debug_time_kernel). */
 double kg_kernel_bytes(const kg_plan_t *plan, int kernel);

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstddef>
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
@@ -218,6 +219,9 @@ kg_status spec_out(kg_plan_s *pl, double *spec, int on_device)
     return KG_OK;
 }
 
+// What stopped a run: a blow-up, or the energy alarm (kg_set_energy_alarm).
+kg_status stop_status(const Ctl &c) { return c.flag == 2 ? KG_E_ENERGY : KG_BLOWUP; }
+
 kg_status read_ctl(kg_plan_s *pl, Ctl &c)
 {
     HIPCHK(pl, hipMemcpyAsync(&c, pl->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, pl->stream));
@@ -231,7 +235,7 @@ void finalize(Plan &p, int nC, double thr, int mode)
     hipLaunchKernelGGL(k_reduce_partials, dim3(RSUB), dim3(256), 0, p.stream, p.partA, (int)p.nA,
                        p.partC, nC, p.sub, p.ctl, mode != 2 ? 1 : 0);
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RSUB), 0, p.stream, p.sub, p.rec, p.ctl, thr,
-                       p.escale, p.h3, mode);
+                       p.escale, p.h3, p.chi, mode);
 }
 
 // Q <- inverse z transform of level S (scaled by 1/M): the resting state of
@@ -362,6 +366,7 @@ const char *kg_status_str(kg_status s)
     case KG_E_NOMEM: return "KG_E_NOMEM";
     case KG_E_HIP: return "KG_E_HIP";
     case KG_BLOWUP: return "KG_BLOWUP";
+    case KG_E_ENERGY: return "KG_E_ENERGY";
     }
     return "unknown status";
 }
@@ -511,6 +516,7 @@ kg_status kg_set_state(kg_plan_t *plan, const double *u0, const double *aux, int
 
     Ctl c0{};
     c0.blow_step = -1;
+    c0.e_tol = p.e_tol;
     HIPCHK(plan, hipMemcpyAsync(p.ctl, &c0, sizeof(Ctl), hipMemcpyHostToDevice, p.stream));
     // FP64: v^m lives in S[m % 2] (v^0 -> S[0], v^{-1} -> S[1]).
     // FP32: S[0] = v^0, S[1] = Delta^0 = v^0 - v^{-1}.
@@ -690,7 +696,7 @@ kg_status kg_step(kg_plan_t *plan, int nsteps, unsigned flags, int *steps_done)
             kg_status s = read_ctl(plan, c);
             if (s != KG_OK) return s;
             if (steps_done) *steps_done = c.step;
-            if (c.flag) return KG_BLOWUP;
+            if (c.flag) return stop_status(c);
         }
         return KG_OK;
     }
@@ -734,7 +740,7 @@ kg_status kg_step(kg_plan_t *plan, int nsteps, unsigned flags, int *steps_done)
         kg_status s = read_ctl(plan, c);
         if (s != KG_OK) return s;
         if (steps_done) *steps_done = c.step;
-        if (c.flag) return KG_BLOWUP;
+        if (c.flag) return stop_status(c);
     }
     return KG_OK;
 }
@@ -755,7 +761,7 @@ kg_status kg_energy(kg_plan_t *plan, double *E, double *t)
     Ctl c;
     kg_status s = read_ctl(plan, c);
     if (s != KG_OK) return s;
-    if (c.flag) return KG_BLOWUP;
+    if (c.flag) return stop_status(c);
     double e = 0.0;
     if ((s = energies(plan, c, c.step, 1, &e)) != KG_OK) return s;
     if (E) *E = e;
@@ -815,6 +821,19 @@ kg_status kg_stats(kg_plan_t *plan, int *steps_done, int *blown_up, int *blowup_
         HIPCHK(plan, hipMemcpy(&r, p.rec + (c.step & (RING - 1)), sizeof r, hipMemcpyDeviceToHost));
         *max_abs_u = r.maxu;
     }
+    return KG_OK;
+}
+
+kg_status kg_set_energy_alarm(kg_plan_t *plan, double rel_tol)
+{
+    if (!plan || !(rel_tol >= 0.0) || !std::isfinite(rel_tol)) return KG_E_INVALID;
+    Plan &p = P(plan);
+    p.e_tol = rel_tol;
+    // The step graphs read the tolerance from the control block as they run,
+    // so no graph is captured again.
+    HIPCHK(plan, hipMemcpyAsync((char *)p.ctl + offsetof(Ctl, e_tol), &p.e_tol, sizeof(double),
+                                hipMemcpyHostToDevice, p.stream));
+    HIPCHK(plan, hipStreamSynchronize(p.stream));
     return KG_OK;
 }
 
@@ -894,7 +913,7 @@ struct SaveHeader {
     double dt, L;
     int64_t s_bytes;
 };
-static const uint64_t KG_MAGIC = 0x4b47535441544531ull;  // "KGSTATE1"
+static const uint64_t KG_MAGIC = 0x4b47535441544532ull;  // "KGSTATE2"
 
 size_t kg_state_bytes(const kg_plan_t *plan)
 {
@@ -945,6 +964,7 @@ kg_status kg_load_state(kg_plan_t *plan, const void *host_buf, size_t bytes)
     Ctl c;
     std::memcpy(&c, b, sizeof c);
     b += sizeof c;
+    c.e_tol = p.e_tol;  // the alarm setting belongs to the plan, not the saved run
     Rec r;
     std::memcpy(&r, b, sizeof r);
     HIPCHK(plan, hipMemcpy(p.ctl, &c, sizeof c, hipMemcpyHostToDevice));
@@ -1054,6 +1074,47 @@ kg_status kg_debug_time_kernel(kg_plan_t *plan, int kernel, int reps, float *ms)
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     p.ready = false;  // the time levels no longer form a valid pair
+    return KG_OK;
+}
+
+kg_status kg_debug_scale_mode(kg_plan_t *plan, int kx, int ky, int kz, double factor)
+{
+    if (!plan) return KG_E_INVALID;
+    Plan &p = P(plan);
+    if (!p.ready) return fail(plan, KG_E_INVALID, "kg_set_state has not been called");
+    if (kx < 0 || kx >= p.H || ky < 0 || ky >= p.n || kz < 0 || kz >= p.n || !std::isfinite(factor))
+        return fail(plan, KG_E_INVALID, "mode index or factor out of range");
+    Ctl c;
+    kg_status s = read_ctl(plan, c);
+    if (s != KG_OK) return s;
+    if (c.flag) return stop_status(c);
+    // the state layout [ky][kx tile][kz][kx within the tile]
+    const size_t off = (size_t)((((long)ky * p.ntx + kx / p.W) * p.n + kz) * p.W + kx % p.W) * p.esz;
+    if (increment(p)) {
+        // FP32: S[0] = v^n, S[1] = Delta^n = v^n - v^{n-1}; v^{n-1} is kept
+        float v[2], d[2];
+        HIPCHK(plan, hipMemcpy(v, p.S[0] + off, sizeof v, hipMemcpyDeviceToHost));
+        HIPCHK(plan, hipMemcpy(d, p.S[1] + off, sizeof d, hipMemcpyDeviceToHost));
+        for (int i = 0; i < 2; ++i) {
+            const double old = v[i];
+            v[i] = (float)(factor * old);
+            d[i] = (float)((double)d[i] + ((double)v[i] - old));
+        }
+        HIPCHK(plan, hipMemcpy(p.S[0] + off, v, sizeof v, hipMemcpyHostToDevice));
+        HIPCHK(plan, hipMemcpy(p.S[1] + off, d, sizeof d, hipMemcpyHostToDevice));
+    } else {
+        double v[2];
+        char *S = p.S[c.step & 1];
+        HIPCHK(plan, hipMemcpy(v, S + off, sizeof v, hipMemcpyDeviceToHost));
+        v[0] *= factor;
+        v[1] *= factor;
+        HIPCHK(plan, hipMemcpy(S + off, v, sizeof v, hipMemcpyHostToDevice));
+    }
+    // the resting field of the changed level, which the next step starts from
+    const void *Sc, *Ssub;
+    stored_level(p, c, 0, Sc, Ssub);
+    if ((s = prepare_q(plan, Sc, Ssub)) != KG_OK) return s;
+    HIPCHK(plan, hipStreamSynchronize(p.stream));
     return KG_OK;
 }
 

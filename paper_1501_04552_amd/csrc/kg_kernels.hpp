@@ -25,13 +25,15 @@ namespace kg {
 
 // Device-side control block and per-level record.
 struct Ctl {
-    int flag;       // nonzero once the run has blown up
-    int step;       // levels completed (the blown level once flag is set)
-    int blow_step;  // level at which blow-up was detected, -1 if none
+    int flag;       // 0 running; 1 blown up; 2 stopped by the energy alarm
+    int step;       // levels completed (the stopping level once flag is set)
+    int blow_step;  // level at which the run stopped, -1 if none
     int pad;
     double elin_m;  // linear energy of the initial pair (v^{-1}, v^0)
     double q4_m;    // h^3 sum (u^{-1})^4
     double maxu_m;  // max |u^{-1}|
+    double e_ref;   // E^{-1/2}, the energy of the initial pair (set by the first step)
+    double e_tol;   // energy alarm: relative drift that stops the run (0: off)
     double pad2;
 };
 struct Rec {
@@ -161,7 +163,7 @@ template <typename T, int N, int MODE>
 __device__ __forceinline__ void xbody(const XArgs<T> &a, long blk, cx<T> *rows, double *part)
 {
     using C = XCfg<T, N>;
-    constexpr int E = Radix<N>::E, TPL = C::TPL, PPB = C::PPB, RS = C::RS, NH = N / 2;
+    constexpr int E = Radix<N>::E, TPL = C::TPL, PPB = C::PPB, RS = C::RS;
     // a pair's threads never span two waves, so its stages sync per wave
     constexpr int XSY = (64 % TPL == 0) ? SYNC_WAVE : SYNC_BLOCK;
     static_assert(E % 2 == 0 && E * TPL == N, "the half-spectrum cases are split by position");
@@ -1047,11 +1049,18 @@ static __global__ __launch_bounds__(256) void k_reduce_partials(const double *pa
     }
 }
 
-//   mode 0 (step):   rec[step] = {elin, q4, maxu}; blow-up test; step counter.
+//   mode 0 (step):   rec[step] = {elin, q4, maxu}; blow-up test; energy
+//                    alarm; step counter.
 //   mode 1 (reduce): rec[step].q4/maxu from the x-pass partials only.
 //   mode 2 (init):   ctl->elin_m, q4_m, maxu_m.
+// The energy alarm follows the paper's use of the conserved energy (Sec. 1.1)
+// as a check on the code and the machine: at level n the step has everything
+// for E^{n-1/2} = elin(v^{n-1}, v^n) - chi (Q4^{n-1} + Q4^n)/8, evaluated in
+// the same order as the host's energy series, so the alarm and kg_energies
+// see the same value.  The first step stores E^{-1/2} as the reference.
 static __global__ __launch_bounds__(RSUB) void k_finalize(const double *sub, Rec *rec, Ctl *ctl,
-                                                   double thr, double escale, double h3, int mode)
+                                                   double thr, double escale, double h3,
+                                                   double chi, int mode)
 {
     if (mode != 2 && ctl->flag) return;
     __shared__ double red[3][RSUB];
@@ -1085,9 +1094,20 @@ static __global__ __launch_bounds__(RSUB) void k_finalize(const double *sub, Rec
     if (bad || (thr > 0.0 && maxu > thr)) {
         ctl->flag = 1;
         ctl->blow_step = n;
-    } else {
-        ctl->step = n + 1;
+        return;
     }
+    const Rec *rp = rec + ((n - 1) & (RING - 1));
+    const double ep = n == 0 ? ctl->elin_m : rp->elin;
+    const double qp = n == 0 ? ctl->q4_m : rp->q4;
+    const double E = ep - chi * (qp + q4) / 8.0;
+    if (n == 0) {
+        ctl->e_ref = E;
+    } else if (ctl->e_tol > 0.0 && !(fabs(E - ctl->e_ref) <= ctl->e_tol * fabs(ctl->e_ref))) {
+        ctl->flag = 2;  // a non-finite energy trips it too
+        ctl->blow_step = n;
+        return;
+    }
+    ctl->step = n + 1;
 }
 
 // Plain copy (bandwidth ceiling and counter calibration): every byte read and

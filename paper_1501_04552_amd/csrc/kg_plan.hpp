@@ -26,6 +26,7 @@ struct kg_plan_s {
     long PZ = 0;  // plane pitch of Q in elements (n * P plus optional padding)
     int zslab = 0;  // z planes per slab of the y-inverse / x / y-forward chain
     double L = 0, h3 = 0, ks2 = 0, invM = 0, escale = 0, chi = 1;
+    double e_tol = 0;  // energy alarm tolerance (kg_set_energy_alarm), 0 when off
     size_t esz = 16;
     hipStream_t stream = nullptr;
     void *ws = nullptr;

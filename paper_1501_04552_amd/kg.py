@@ -19,7 +19,7 @@ if not os.path.exists(LIB):
 
 _lib = ctypes.CDLL(LIB)
 
-KG_OK, KG_E_INVALID, KG_E_UNSUPPORTED_SIZE, KG_E_NOMEM, KG_E_HIP, KG_BLOWUP = range(6)
+KG_OK, KG_E_INVALID, KG_E_UNSUPPORTED_SIZE, KG_E_NOMEM, KG_E_HIP, KG_BLOWUP, KG_E_ENERGY = range(7)
 KG_FP64, KG_FP32 = 0, 1
 KG_INIT_VELOCITY, KG_INIT_TWO_LEVEL = 0, 1
 KG_STEP_SYNC = 1
@@ -71,6 +71,7 @@ _SIGS = {
     "kg_records": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]),
     "kg_energies": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp]),
     "kg_stats": (ctypes.c_int, [_vp, _ip, _ip, _ip, _dp]),
+    "kg_set_energy_alarm": (ctypes.c_int, [_vp, ctypes.c_double]),
     "kg_get_u": (ctypes.c_int, [_vp, _vp, ctypes.c_int]),
     "kg_get_state": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int]),
     "kg_get_spectrum": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.c_int]),
@@ -84,6 +85,8 @@ _SIGS = {
                                             ctypes.POINTER(ctypes.c_float)]),
     "kg_debug_copy": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, ctypes.c_int, _vp,
                                      ctypes.POINTER(ctypes.c_float)]),
+    "kg_debug_scale_mode": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                           ctypes.c_double]),
     "kg_kernel_bytes": (ctypes.c_double, [_vp, ctypes.c_int]),
     "kg_kernel_times": (ctypes.c_int, [_vp, _dp, _ip]),
     "kg_batch_run": (ctypes.c_int, [ctypes.POINTER(kg_run_desc), ctypes.c_int,
@@ -173,14 +176,14 @@ def kg_set_state(plan, u0, aux=None, mode=KG_INIT_VELOCITY):
 def kg_step(plan, nsteps, flags=0):
     done = ctypes.c_int(-1)
     st = _check(_lib.kg_step(plan, nsteps, flags, ctypes.byref(done)), plan,
-                allow=(KG_OK, KG_BLOWUP))
+                allow=(KG_OK, KG_BLOWUP, KG_E_ENERGY))
     return st, done.value
 
 
 def kg_energy(plan):
     E, t = ctypes.c_double(), ctypes.c_double()
     st = _check(_lib.kg_energy(plan, ctypes.byref(E), ctypes.byref(t)), plan,
-                allow=(KG_OK, KG_BLOWUP))
+                allow=(KG_OK, KG_BLOWUP, KG_E_ENERGY))
     return (E.value, t.value) if st == KG_OK else (float("nan"), float("nan"))
 
 
@@ -199,14 +202,19 @@ def kg_energies(plan, first, count):
 
 
 def kg_stats(plan, max_abs_u=False):
-    """(steps done, blown up, blown level or -1), plus max|u^n| of the newest
-    level when max_abs_u is true."""
+    """(steps done, stop flag (0 running, 1 blown up, 2 energy alarm), the
+    level the run stopped at or -1), plus max|u^n| of the newest level when
+    max_abs_u is true."""
     s, b, bs, mx = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
     _check(_lib.kg_stats(plan, ctypes.byref(s), ctypes.byref(b), ctypes.byref(bs),
                          ctypes.byref(mx) if max_abs_u else None), plan)
     if max_abs_u:
-        return s.value, bool(b.value), bs.value, mx.value
-    return s.value, bool(b.value), bs.value
+        return s.value, b.value, bs.value, mx.value
+    return s.value, b.value, bs.value
+
+
+def kg_set_energy_alarm(plan, rel_tol):
+    _check(_lib.kg_set_energy_alarm(plan, float(rel_tol)), plan)
 
 
 def kg_get_u(plan, n, out=None, complex_field=False):
@@ -284,6 +292,11 @@ def kg_debug_time_kernel(plan, kernel, reps):
     ms = ctypes.c_float()
     _check(_lib.kg_debug_time_kernel(plan, kernel, reps, ctypes.byref(ms)), plan)
     return ms.value
+
+
+def kg_debug_scale_mode(plan, kx, ky, kz, factor):
+    return _check(_lib.kg_debug_scale_mode(plan, kx, ky, kz, float(factor)), plan,
+                  allow=(KG_OK, KG_BLOWUP, KG_E_ENERGY))
 
 
 def kg_debug_copy(dst_ptr, src_ptr, nbytes, reps, stream=None):

@@ -76,6 +76,10 @@ class Solver:
     def stats(self, max_abs_u=False):
         return _kg.kg_stats(self.plan, max_abs_u)
 
+    def energy_alarm(self, rel_tol):
+        """Stop the run once the energy drifts by more than rel_tol (0: off)."""
+        _kg.kg_set_energy_alarm(self.plan, rel_tol)
+
     def state(self):
         """(u^{n-1}, u^n) on the host."""
         return _kg.kg_get_state(self.plan, self.n, complex_field=self.complex_field)
