@@ -3,7 +3,7 @@
 The oracle is the reference every GPU result is checked against, so its own
 memory and arithmetic must be sound: out-of-bounds accesses, leaks, integer
 overflow in index arithmetic and other undefined behaviour would make its
-answers unreliable without failing its pins.  The driver
+answers unreliable without failing its pins.  The test program
 (tests/oracle_sanitize_driver.c) calls every entry point on small inputs:
 each line length class of the transform, both start rules, linear and
 nonlinear runs with and without the 2/3 truncation, a blow-up, the complex
