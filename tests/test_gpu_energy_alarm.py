@@ -148,14 +148,16 @@ def test_alarm_setting_and_reference_survive_state_calls(kg):
         assert st == kg.KG_OK and done == 6
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_scale_mode_changes_one_coefficient(kg, precision):
+@pytest.mark.parametrize("precision,complex_field", [(0, False), (1, False), (0, True),
+                                                     (1, True)])
+def test_scale_mode_changes_one_coefficient(kg, precision, complex_field):
     """The forced fault multiplies exactly one stored coefficient of v^n and
-    leaves v^{n-1} as it was."""
+    leaves v^{n-1} as it was (complex fields: the full spectrum, kx up to n)."""
     n, dt = 24, 0.01
-    kx, ky, kz, f = 3, 5, 20, 1.25
-    with kg.Solver(n, dt, precision=precision) as s:
-        s.set_state(ki.gaussian(n, 1.0))
+    kx, ky, kz, f = (19 if complex_field else 3), 5, 20, 1.25
+    with kg.Solver(n, dt, precision=precision, complex_field=complex_field) as s:
+        u0 = ki.gaussian(n, 1.0)
+        s.set_state(u0 * np.exp(0.5j * ki.axis(n)) if complex_field else u0)
         s.step(7)
         v0, w0 = s.spectrum(0), s.spectrum(1)
         assert kg.kg_debug_scale_mode(s.plan, kx, ky, kz, f) == kg.KG_OK

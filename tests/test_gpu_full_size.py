@@ -94,14 +94,15 @@ def test_fp64_matches_oracle_at_full_size(kg, n, A):
             compare_series(s, g, m, 1e-11, 1e-11)
 
 
-@pytest.mark.parametrize("n,steps", [(256, 200), (384, 100), (512, 200)])
-def test_fp32_matches_oracle_at_full_size(kg, n, steps):
+@pytest.mark.parametrize("n,A,steps", [(256, 1.5, 200), (384, 1.5, 100), (512, 1.5, 200),
+                                       (512, 0.1, 500)])
+def test_fp32_matches_oracle_at_full_size(kg, n, A, steps):
     """The precision workload: A = 1.5, sigma = 1, dt = 0.005, 200 steps in
     FP32 against the FP64 oracle (384^3: its radix-3 lines and slab chain in
-    FP32, 100 steps)."""
-    g = load(n, 1.5)
+    FP32, 100 steps); and the benchmark's 500-step A = 0.1 run in FP32."""
+    g = load(n, A)
     with kg.Solver(n, float(g["dt"]), blowup_threshold=1e3, precision=kg.KG_FP32) as s:
-        s.set_state(torch.from_numpy(ki.gaussian(n, 1.5)).cuda())
+        s.set_state(torch.from_numpy(ki.gaussian(n, A)).cuda())
         st, done = s.step(steps)
         assert st == kg.KG_OK and done == steps
         compare_level(s, g, n, steps, 1e-4)
