@@ -270,13 +270,17 @@ typedef struct {
     double threshold; /* <= 0: no blow-up test */
 } kg_run_desc;
 
+/* Every level 0..max_steps is tested for blow-up, the last one included (a run
+ * of zero steps tests level 0), as the oracle's runs do. */
 typedef struct {
     int blew_up;      /* 1 if a level n <= max_steps blew up */
     int steps_done;   /* the blown level n, else max_steps */
     double t_blowup;  /* n * dt for a blow-up, else -1 */
     double E0;        /* E^{-1/2} of the initial pair (see kg_energy) */
-    double E_final;   /* E^{n-1/2} at n = max_steps (NaN after a blow-up) */
-    double max_abs_u; /* max of max|u^m| over the levels m computed (NaN if non-finite) */
+    double E_final;   /* E^{n-1/2} at n = max_steps (E0 when max_steps = 0; NaN
+                         after a blow-up) */
+    double max_abs_u; /* max of max|u^m| over the levels m = 0..steps_done (NaN if
+                         non-finite) */
 } kg_run_result;
 
 typedef struct {

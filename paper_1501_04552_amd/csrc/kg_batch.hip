@@ -268,7 +268,7 @@ kg_status setup(Batch &b, const kg_run_desc *runs, int nruns, const std::map<int
         R.W = tune.at(d.n).W;
         R.ntx = (R.H + R.W - 1) / R.W;
         R.P = ((R.ntx * R.W + 7) / 8) * 8;
-        R.flag = d.max_steps > 0 ? 0 : 2;
+        R.flag = 0;  // runs of zero steps retire after the set-up (run_batch)
         R.step = 0;
         R.max_steps = d.max_steps;
         R.blow_step = -1;
@@ -551,6 +551,19 @@ kg_status run_batch(const kg_run_desc *runs, int nruns, const std::map<int, Tune
     if (s != KG_OK) return s;
     if ((s = init(b)) != KG_OK) return s;
     BCHK(hipStreamSynchronize(st));
+    // Runs of zero steps are set up like the others, so the final reduction
+    // finds their level 0 (its energy, max|u| and blow-up test), and retire
+    // before the first step.
+    bool unstepped = false;
+    for (int r = 0; r < nruns; ++r) unstepped = unstepped || runs[r].max_steps == 0;
+    if (unstepped) {
+        BCHK(hipMemcpyAsync(b.host.data(), b.d_runs, sizeof(BRun) * nruns, hipMemcpyDeviceToHost, st));
+        BCHK(hipStreamSynchronize(st));
+        for (BRun &R : b.host)
+            if (R.flag == 0 && R.max_steps == 0) R.flag = 2;
+        BCHK(hipMemcpyAsync(b.d_runs, b.host.data(), sizeof(BRun) * nruns, hipMemcpyHostToDevice, st));
+        BCHK(hipStreamSynchronize(st));
+    }
     int max_steps = 0;
     for (int r = 0; r < nruns; ++r) max_steps = std::max(max_steps, runs[r].max_steps);
     const auto t0 = std::chrono::steady_clock::now();
@@ -746,10 +759,6 @@ kg_status kg_batch_run(const kg_run_desc *runs, int nruns, kg_run_result *out,
         o.E0 = R.E0;
         o.E_final = R.flag == 1 ? std::nan("") : R.E_final;
         o.max_abs_u = R.maxu_max;
-        if (R.max_steps == 0) {
-            o.E0 = std::nan("");
-            o.E_final = std::nan("");
-        }
     }
     return KG_OK;
 }

@@ -208,8 +208,18 @@ __global__ __launch_bounds__(256) void kb_finalize(BRun *runs, const int *list, 
                 R.q4_m = q4;
                 R.maxu_max = 0.0;
             } else if (mode == BF_FINAL) {
-                R.E_final = R.elin_last - R.chi * (R.q4_cur + q4) / 8.0;
-                R.maxu_max = nanmax(R.maxu_max, maxu);
+                // the last level max_steps: its energy, and the blow-up test
+                // every other level had (level 0 itself for zero-step runs)
+                const int m = R.step;
+                const double E = m == 0 ? R.elin_m - R.chi * (R.q4_m + q4) / 8.0
+                                        : R.elin_last - R.chi * (R.q4_cur + q4) / 8.0;
+                if (m == 0) R.E0 = E;
+                R.E_final = E;
+                R.maxu_max = nanmax(R.maxu_max, bad ? __builtin_nan("") : maxu);
+                if (bad || (R.thr > 0.0 && maxu > R.thr)) {
+                    R.flag = 1;
+                    R.blow_step = m;
+                }
             } else {
                 const int m = R.step;
                 if (m == 0) R.E0 = R.elin_m - R.chi * (R.q4_m + q4) / 8.0;

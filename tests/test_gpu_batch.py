@@ -162,6 +162,62 @@ def test_batch_sweep_sizes_and_autotuner(kg, tmp_path):
             assert not b["blew_up"] and b["steps_done"] == 40
 
 
+def test_batch_tests_every_level_like_the_oracle(kg):
+    """The oracle tests every level 0..nsteps for blow-up, the last one too,
+    and so must the sweep: a run whose blow-up level b equals max_steps is
+    blown at b; with max_steps = b - 1 it finishes with the oracle's energy.
+    Runs of zero steps report the initial pair's energy and max|u^0|, and one
+    whose u0 already exceeds the threshold is blown at level 0, as is the same
+    data given steps.  Close to a blow-up the run amplifies rounding, so the
+    levels next to b are held to 1e-8 (E) and 1e-6 (max|u| above 1e3)
+    instead of 1e-11."""
+    dt, thr = 0.01, 1e3
+    base = dict(n=32, A=4.0, sigma=(1.0, 1.2, 0.9), dt=dt, threshold=thr)
+    u0 = ki.gaussian(32, base["A"], base["sigma"])
+    ref = oracle.run(u0, dt, 400, threshold=thr)
+    b = ref["blowup_step"]
+    assert b > 2
+    big = dict(base, A=2000.0)
+    ref_big = oracle.run(ki.gaussian(32, big["A"], big["sigma"]), dt, 0, threshold=thr)
+    assert ref_big["blowup_step"] == 0
+    calm = dict(base, A=1.0, max_steps=20)
+    ref_calm = oracle.run(ki.gaussian(32, calm["A"], calm["sigma"]), dt, 20, threshold=thr)
+    runs = [dict(base, max_steps=b), dict(base, max_steps=b - 1), dict(base, max_steps=0),
+            dict(big, max_steps=0), dict(big, max_steps=5), calm]
+    res, _ = kg.kg_batch_run(runs)
+    at_b, before_b, zero, big0, big5, calm_r = res
+    rel = lambda x, y: abs(x - y) / abs(y)
+    # blown exactly at its last level
+    assert at_b["blew_up"] and at_b["steps_done"] == b and abs(at_b["t_blowup"] - b * dt) < 1e-12
+    assert np.isnan(at_b["E_final"]) and at_b["max_abs_u"] > thr
+    assert rel(at_b["max_abs_u"], np.max(ref["maxu"][:b + 1])) <= 1e-6
+    # one step fewer: finished, with the oracle's energy of that level
+    assert not before_b["blew_up"] and before_b["steps_done"] == b - 1
+    assert rel(before_b["E_final"], ref["energy"][b - 1]) <= 1e-8
+    assert rel(before_b["max_abs_u"], np.max(ref["maxu"][:b])) <= 1e-8
+    # zero steps: level 0 only
+    assert not zero["blew_up"] and zero["steps_done"] == 0 and zero["t_blowup"] == -1.0
+    assert rel(zero["E0"], ref["energy"][0]) <= 1e-11 and zero["E_final"] == zero["E0"]
+    assert rel(zero["max_abs_u"], ref["maxu"][0]) <= 1e-11
+    for r in (at_b, before_b):
+        assert rel(r["E0"], ref["energy"][0]) <= 1e-11
+    # u0 above the threshold: blown at level 0 with or without steps
+    for r in (big0, big5):
+        assert r["blew_up"] and r["steps_done"] == 0 and r["t_blowup"] == 0.0
+        assert np.isnan(r["E_final"])
+        assert rel(r["E0"], ref_big["energy"][0]) <= 1e-11
+        assert rel(r["max_abs_u"], ref_big["maxu"][0]) <= 1e-11
+    # an ordinary run in the same batch is unaffected
+    assert not calm_r["blew_up"] and calm_r["steps_done"] == 20
+    assert rel(calm_r["E_final"], ref_calm["energy"][20]) <= 1e-11
+
+
+def test_batch_rejects_an_empty_batch(kg):
+    with pytest.raises(kg.KGError) as e:
+        kg.kg_batch_run([])
+    assert e.value.status == kg.KG_E_INVALID
+
+
 def test_batch_rejects_bad_descriptors(kg):
     with pytest.raises(kg.KGError) as e:
         kg.kg_batch_run([dict(n=40, A=1, sigma=(1, 1, 1), dt=0.01, max_steps=5, threshold=0)])
