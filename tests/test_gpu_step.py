@@ -456,3 +456,33 @@ def test_persistent_z_pass_matches_tile_kernel(kg, monkeypatch, precision, n):
     assert np.array_equal(a[3], b[3]) and np.array_equal(a[4], b[4])
     assert np.allclose(a[2], b[2], rtol=1e-14, atol=0)
     assert abs(a[5] - b[5]) <= 1e-14 * abs(b[5])
+
+
+@pytest.mark.parametrize("precision,complex_field", [(0, False), (1, False), (0, True),
+                                                     (1, True)])
+def test_zero_field_stays_zero(kg, precision, complex_field):
+    """The zero field is a solution of eq. (2): every level, max|u| and the
+    energy stay exactly 0, and an energy alarm (reference E = 0) never trips."""
+    n, steps = 24, 20
+    u0 = np.zeros((n, n, n), np.complex128 if complex_field else np.float64)
+    with kg.Solver(n, 0.01, precision=precision, complex_field=complex_field,
+                   blowup_threshold=1e3) as s:
+        s.energy_alarm(1e-12)
+        s.set_state(u0)
+        st, done = s.step(steps)
+        assert st == kg.KG_OK and done == steps
+        assert not np.any(s.spectrum(0)) and not np.any(s.spectrum(1))
+        assert not np.any(s.u())
+        assert np.all(s.energies(0, steps + 1) == 0.0)
+        elin, q4, maxu = s.records(0, steps)
+        assert not np.any(elin) and not np.any(q4) and not np.any(maxu)
+
+
+def test_zero_amplitude_run_in_a_sweep(kg):
+    res, _ = kg.kg_batch_run([dict(n=32, A=0.0, sigma=(1, 1, 1), dt=0.01, max_steps=15,
+                                   threshold=1e3),
+                              dict(n=48, A=0.0, sigma=(1, 2, 1), dt=0.01, max_steps=0,
+                                   threshold=1e3)])
+    for r, m in zip(res, (15, 0)):
+        assert not r["blew_up"] and r["steps_done"] == m
+        assert r["E0"] == 0.0 and r["E_final"] == 0.0 and r["max_abs_u"] == 0.0
