@@ -486,3 +486,38 @@ def test_zero_amplitude_run_in_a_sweep(kg):
     for r, m in zip(res, (15, 0)):
         assert not r["blew_up"] and r["steps_done"] == m
         assert r["E0"] == 0.0 and r["E_final"] == 0.0 and r["max_abs_u"] == 0.0
+
+
+@pytest.mark.parametrize("n,precision", [(32, 0), (24, 0), (32, 1)])
+def test_other_box_length_matches_oracle(kg, n, precision):
+    """A box of side 10 instead of 8 pi (the wavenumbers, h^3 and the sampled
+    grid all change): the nonlinear Gaussian after 30 steps against the
+    oracle, FP64 to 1e-11 and FP32 to 1e-4, energies alike."""
+    Lb, dt, steps = 10.0, 0.01, 30
+    u0 = ki.gaussian(n, 1.2, (0.9, 1.1, 1.3), L=Lb)
+    ref = oracle.run(u0, dt, steps, L=(Lb,) * 3)
+    tol = 1e-11 if precision == 0 else 1e-4
+    with kg.Solver(n, dt, L=Lb, precision=precision) as s:
+        s.set_state(u0)
+        st, done = s.step(steps)
+        assert st == kg.KG_OK and done == steps
+        assert rel_l2(s.u(), ref["u"]) <= tol
+        E = s.energies(0, steps + 1)
+        assert np.max(np.abs(E - ref["energy"]) / np.abs(ref["energy"])) <= tol
+
+
+def test_other_box_length_in_a_sweep(kg):
+    Lb = 10.0
+    runs = [dict(n=32, A=1.2, sigma=(0.9, 1.1, 1.3), dt=0.01, max_steps=30, threshold=1e3),
+            dict(n=48, A=4.0, sigma=(1.0, 1.2, 0.9), dt=0.01, max_steps=300, threshold=1e3)]
+    res, _ = kg.kg_batch_run(runs, L=Lb)
+    for r, b in zip(runs, res):
+        ref = oracle.run(ki.gaussian(r["n"], r["A"], r["sigma"], L=Lb), r["dt"], r["max_steps"],
+                         L=(Lb,) * 3, threshold=r["threshold"])
+        assert b["blew_up"] == (ref["blowup_step"] >= 0)
+        assert abs(b["E0"] - ref["energy"][0]) <= 1e-11 * abs(ref["energy"][0])
+        if b["blew_up"]:
+            assert b["steps_done"] == ref["blowup_step"]
+        else:
+            E = ref["energy"][r["max_steps"]]
+            assert abs(b["E_final"] - E) <= 1e-11 * abs(E)
