@@ -521,3 +521,25 @@ def test_other_box_length_in_a_sweep(kg):
         else:
             E = ref["energy"][r["max_steps"]]
             assert abs(b["E_final"] - E) <= 1e-11 * abs(E)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_large_time_step_linear(kg, precision):
+    """dt = 0.5 (a_k = omega_k^2 dt^2 / 4 from 0.06 to 3.1, so alpha_k runs
+    from 1.76 down to -1.0): the semi-implicit scheme of eq. (2) keeps the
+    linear energy of Sec. 1.1 exactly for any dt, and the GPU follows the
+    oracle (FP64 1e-11; FP32 1e-4, its energy to 1e-6)."""
+    n, dt, steps = 32, 0.5, 40
+    u0 = ki.gaussian(n, 0.7, (1.3, 0.8, 1.0))
+    ref = oracle.run(u0, dt, steps, linear_only=True)
+    E_ref = ref["energy"]
+    assert np.max(np.abs(E_ref - E_ref[0])) <= 1e-12 * abs(E_ref[0])
+    tol, etol = (1e-11, 1e-12) if precision == 0 else (1e-4, 1e-6)
+    with kg.Solver(n, dt, linear_only=True, precision=precision) as s:
+        s.set_state(u0)
+        st, done = s.step(steps)
+        assert st == kg.KG_OK and done == steps
+        assert rel_l2(s.u(), ref["u"]) <= tol
+        E = s.energies(0, steps + 1)
+        assert np.max(np.abs(E - E[0])) <= etol * abs(E[0])
+        assert np.max(np.abs(E - E_ref)) <= max(etol, 1e-11) * abs(E_ref[0])
