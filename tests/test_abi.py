@@ -54,6 +54,12 @@ def test_host_side_validation():
     with pytest.raises(kg.KGError) as e:
         kg.kg_plan(kg.make_params(64, 0.0))
     assert e.value.status == kg.KG_E_INVALID
+    # a borrowed workspace smaller than kg_workspace_bytes is refused before
+    # the plan touches it (the pointer is never dereferenced)
+    need = kg.kg_workspace_bytes(kg.make_params(32, 0.01))
+    with pytest.raises(kg.KGError) as e:
+        kg.kg_plan(kg.make_params(32, 0.01), 0x10000, need - 1)
+    assert e.value.status == kg.KG_E_NOMEM
 
 
 def test_plan_setup_runs_on_the_host():

@@ -543,3 +543,24 @@ def test_large_time_step_linear(kg, precision):
         E = s.energies(0, steps + 1)
         assert np.max(np.abs(E - E[0])) <= etol * abs(E[0])
         assert np.max(np.abs(E - E_ref)) <= max(etol, 1e-11) * abs(E_ref[0])
+
+
+def test_library_owned_workspace_matches_borrowed(kg):
+    """kg_plan with no workspace allocates and owns its own; the run is
+    bitwise the run in a caller's workspace."""
+    n, dt, steps = 32, 0.01, 25
+    u0 = ki.gaussian(n, 1.2)
+    plan = kg.kg_plan(kg.make_params(n, dt))
+    try:
+        kg.kg_set_state(plan, u0)
+        st, done = kg.kg_step(plan, steps, kg.KG_STEP_SYNC)
+        assert st == kg.KG_OK and done == steps
+        E = kg.kg_energies(plan, 0, steps + 1)
+        spec = kg.kg_get_spectrum(plan, n, 0)
+    finally:
+        kg.kg_destroy(plan)
+    with kg.Solver(n, dt) as s:
+        s.set_state(u0)
+        s.step(steps)
+        assert np.array_equal(spec, s.spectrum(0))
+        assert np.array_equal(E, s.energies(0, steps + 1))
