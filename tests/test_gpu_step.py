@@ -564,3 +564,32 @@ def test_library_owned_workspace_matches_borrowed(kg):
         s.step(steps)
         assert np.array_equal(spec, s.spectrum(0))
         assert np.array_equal(E, s.energies(0, steps + 1))
+
+
+def test_asynchronous_steps_match_synchronous(kg):
+    """kg_step without KG_STEP_SYNC only enqueues graph replays (the path the
+    benchmark times): several such calls in a row, then a synchronising
+    query, give bitwise the levels and energies of one synchronous call; past
+    a blow-up the queued replays do nothing and the counter stays at the
+    blown level (the uniform a = 1.5 data blows up at level 145, dt = 0.01)."""
+    n, dt = 32, 0.01
+    u0 = ki.gaussian(n, 1.2)
+    with kg.Solver(n, dt) as a, kg.Solver(n, dt) as b:
+        a.set_state(u0)
+        for k in (7, 1, 8, 19):
+            st, _ = a.step(k, sync=False)
+            assert st == kg.KG_OK
+        b.set_state(u0)
+        st, done = b.step(35)
+        assert st == kg.KG_OK and done == 35
+        assert a.stats() == b.stats() == (35, 0, -1)
+        assert np.array_equal(a.spectrum(0), b.spectrum(0))
+        assert np.array_equal(a.spectrum(1), b.spectrum(1))
+        assert np.array_equal(a.energies(0, 36), b.energies(0, 36))
+    with kg.Solver(8, dt, blowup_threshold=1e3) as s:
+        s.set_state(ki.uniform(8, 1.5))
+        for _ in range(20):
+            s.step(9, sync=False)  # 180 steps queued, the run blows up at 145
+        assert s.stats() == (145, 1, 145)
+        st, done = s.step(1)
+        assert st == kg.KG_BLOWUP and done == 145
